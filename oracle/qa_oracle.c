@@ -1,0 +1,953 @@
+/*
+ * qa_oracle.c -- plain FP64 CPU oracle for the constant-capacitance-model
+ * ground state (van Straaten et al., "QArray", arXiv 2404.04994).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * cpu_baseline leg of the benchmark load this library.  The HIP product path
+ * never links, includes or calls it, and it shares no code, header, table or
+ * constant generator with that path.
+ *
+ * Everything here is deliberately plain: direct formulas, full enumeration,
+ * textbook linear algebra, no blocking and no incremental tricks.
+ *
+ * Model (paper Sec. 2, Eqs. for the potential and the free energy):
+ *   A   = C_dd^{-1}                     (inverse of the Maxwell dot-dot block)
+ *   x_u = C_gd V                        (open continuous minimum, Sec. 3.1)
+ *   U(n) = 1/2 (n - x_u)^T A (n - x_u)  -- the free energy F(n) of Sec. 2 plus a
+ *                                          term independent of n, so it has the
+ *                                          same argmin and Boltzmann weights.
+ *   admissible set: n integer, n >= 0 (open); additionally sum(n) = N_hat
+ *   (closed), constraints (i)-(iii) of Sec. 2.
+ *
+ * Two levels of reference are provided:
+ *   O-exact  : the definition -- argmin / Boltzmann average over all admissible
+ *              n (certified-box brute force, Schnorr-Euchner enumeration,
+ *              composition enumeration for closed arrays).
+ *   O-method : the paper's two-stage algorithm (Sec. 3) replayed in FP64 with
+ *              an exact constrained continuous minimum: analytic solution
+ *              first (Sec. 3.1, App. C/D), exact QP otherwise (Sec. 3.1.2),
+ *              then the floor/ceil candidate box (Sec. 3.2.1) or its
+ *              thresholded subset (Sec. 3.2.2, with threshold doubling for
+ *              closed arrays), then argmin (Eq. argmin) or softargmin
+ *              (Eq. softargmin, Sec. 4.2).
+ *
+ * Readings where the paper is silent or ambiguous (each is listed in the
+ * design notes of the repository):
+ *   R1 floor/ceil box = f + {0,1}^N with f = floor(x*), also when x*_i is an
+ *      exact integer (Sec. 3.2.1 does not say what happens then).
+ *   R2 thresholded: dot i is "free" when |frac(x*_i) - 1/2| <= t/2 (inclusive),
+ *      other dots are rounded to nearest (Sec. 3.2.2).
+ *   R3 closed arrays with no admissible thresholded candidate double t for
+ *      that pixel only; t = 0 jumps straight to t = 1.
+ *   R4 equal energies are resolved towards the lexicographically smallest n
+ *      (dot 0 most significant).
+ *   R5 the softargmin of the method runs over the candidate set the method
+ *      scores; O-exact sums over every admissible state within 40 kT of the
+ *      minimum.
+ *   R6 the QP is solved exactly (the paper uses OSQP; App. J attributes
+ *      artefacts to its finite precision).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXN 16
+#define ORC_MAXS (ORC_MAXN + 1)
+
+/* ---------------------------------------------------------------------- */
+/* small dense linear algebra                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Solve M x = b (m x m, row-major) by Gaussian elimination with partial
+ * pivoting.  M and b are copied.  Returns 0, or -1 when a pivot vanishes. */
+static int gauss_solve(int m, const double *M, const double *b, double *x)
+{
+    double a[ORC_MAXS * ORC_MAXS], r[ORC_MAXS];
+    memcpy(a, M, sizeof(double) * m * m);
+    memcpy(r, b, sizeof(double) * m);
+    for (int c = 0; c < m; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < m; ++i)
+            if (fabs(a[i * m + c]) > fabs(a[piv * m + c])) piv = i;
+        if (a[piv * m + c] == 0.0) return -1;
+        if (piv != c) {
+            for (int j = 0; j < m; ++j) {
+                double t = a[c * m + j]; a[c * m + j] = a[piv * m + j]; a[piv * m + j] = t;
+            }
+            double t = r[c]; r[c] = r[piv]; r[piv] = t;
+        }
+        for (int i = c + 1; i < m; ++i) {
+            double f = a[i * m + c] / a[c * m + c];
+            for (int j = c; j < m; ++j) a[i * m + j] -= f * a[c * m + j];
+            r[i] -= f * r[c];
+        }
+    }
+    for (int i = m - 1; i >= 0; --i) {
+        double s = r[i];
+        for (int j = i + 1; j < m; ++j) s -= a[i * m + j] * x[j];
+        x[i] = s / a[i * m + i];
+    }
+    return 0;
+}
+
+/* A = C^{-1}, one Gaussian solve per column.  Returns 0 or -1. */
+int orc_inverse(int n, const double *C, double *A)
+{
+    if (n < 1 || n > ORC_MAXN) return -1;
+    double e[ORC_MAXS], col[ORC_MAXS];
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) e[i] = (i == j) ? 1.0 : 0.0;
+        if (gauss_solve(n, C, e, col)) return -1;
+        for (int i = 0; i < n; ++i) A[i * n + j] = col[i];
+    }
+    return 0;
+}
+
+/* Upper-triangular R with R^T R = A (Cholesky).  Returns 0, -1 if not PD. */
+static int cholesky_upper(int n, const double *A, double *R)
+{
+    memset(R, 0, sizeof(double) * n * n);
+    for (int i = 0; i < n; ++i) {
+        double s = A[i * n + i];
+        for (int k = 0; k < i; ++k) s -= R[k * n + i] * R[k * n + i];
+        if (!(s > 0.0)) return -1;
+        R[i * n + i] = sqrt(s);
+        for (int j = i + 1; j < n; ++j) {
+            double t = A[i * n + j];
+            for (int k = 0; k < i; ++k) t -= R[k * n + i] * R[k * n + j];
+            R[i * n + j] = t / R[i * n + i];
+        }
+    }
+    return 0;
+}
+
+/* 0 if C is positive definite (Cholesky succeeds), -1 otherwise. */
+int orc_is_pd(int n, const double *C)
+{
+    double R[ORC_MAXN * ORC_MAXN];
+    if (n < 1 || n > ORC_MAXN) return -1;
+    return cholesky_upper(n, C, R);
+}
+
+/* ---------------------------------------------------------------------- */
+/* model                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* x_u = C_gd V for one pixel (open continuous minimum, Sec. 3.1.1). */
+static void pixel_xu(int n, int g, const double *Cgd, const double *V, double *xu)
+{
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < g; ++j) s += Cgd[i * g + j] * V[j];
+        xu[i] = s;
+    }
+}
+
+void orc_xu(int64_t P, int n, int g, const double *Cgd, const double *V, double *xu)
+{
+    for (int64_t p = 0; p < P; ++p) pixel_xu(n, g, Cgd, V + p * g, xu + p * n);
+}
+
+/* U(q) = 1/2 (q - x_u)^T A (q - x_u), the free energy up to a q-independent
+ * constant (Sec. 2, Eq. free_energy, completed square). */
+static double energy_i(int n, const double *A, const double *xu, const int *q)
+{
+    double d[ORC_MAXN], s = 0.0;
+    for (int i = 0; i < n; ++i) d[i] = (double)q[i] - xu[i];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) s += d[i] * A[i * n + j] * d[j];
+    return 0.5 * s;
+}
+
+double orc_energy(int n, const double *A, const double *xu, const int *q)
+{
+    return energy_i(n, A, xu, q);
+}
+
+/* lexicographic order of charge vectors, dot 0 most significant (R4) */
+static int lex_less(int n, const int *a, const int *b)
+{
+    for (int i = 0; i < n; ++i)
+        if (a[i] != b[i]) return a[i] < b[i];
+    return 0;
+}
+
+/* running best / runner-up of (energy, state) pairs */
+typedef struct {
+    double e1, e2;
+    int q1[ORC_MAXN];
+    int n;
+    int64_t count;
+} top2_t;
+
+static void top2_init(top2_t *t, int n)
+{
+    t->e1 = INFINITY; t->e2 = INFINITY; t->n = n; t->count = 0;
+    for (int i = 0; i < n; ++i) t->q1[i] = 0;
+}
+
+static void top2_push(top2_t *t, double e, const int *q)
+{
+    t->count++;
+    if (e < t->e1 || (e == t->e1 && lex_less(t->n, q, t->q1))) {
+        t->e2 = t->e1;
+        t->e1 = e;
+        memcpy(t->q1, q, sizeof(int) * t->n);
+    } else if (e < t->e2) {
+        t->e2 = e;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* continuous minimum                                                      */
+/* ---------------------------------------------------------------------- */
+
+/* analytic minima, ignoring n >= 0:
+ *   open   x = x_u                                          (Sec. 3.1.1, App. C)
+ *   closed x = x_u + (N_hat - 1^T x_u) C_dd 1 / (1^T C_dd 1) (Sec. 3.1.1, App. D) */
+static void analytic_min(int n, const double *Cdd, const double *xu, int closed,
+                         int nhat, double *x)
+{
+    for (int i = 0; i < n; ++i) x[i] = xu[i];
+    if (!closed) return;
+    double c[ORC_MAXN], one_c = 0.0, one_xu = 0.0;
+    for (int i = 0; i < n; ++i) {
+        c[i] = 0.0;
+        for (int j = 0; j < n; ++j) c[i] += Cdd[i * n + j];
+        one_c += c[i];
+        one_xu += xu[i];
+    }
+    double lam = ((double)nhat - one_xu) / one_c;
+    for (int i = 0; i < n; ++i) x[i] = xu[i] + lam * c[i];
+}
+
+void orc_analytic_min(int n, const double *Cdd, const double *xu, int closed, int nhat,
+                      double *x)
+{
+    analytic_min(n, Cdd, xu, closed, nhat, x);
+}
+
+/* KKT form of the QP of Sec. 3.1.2, min U(x) s.t. x >= 0 [, 1^T x = N_hat].
+ * Stationarity A(x - x_u) = mu + lambda 1 multiplied through by C_dd gives
+ *   x = x_u + C_dd mu + lambda C_dd 1,   mu >= 0, x >= 0, mu_i x_i = 0,
+ * (lambda = 0 for open arrays).  For a trial active set S (x_S = 0, mu = 0
+ * off S) the unknowns (mu_S, lambda) solve a linear system; the KKT point is
+ * the S for which the solution has mu_S >= 0 and x >= 0.  U is strictly
+ * convex, so that x is the unique minimiser. */
+static int kkt_for_set(int n, const double *Cdd, const double *xu, int closed, int nhat,
+                       uint32_t S, double *x, double *mu_out, double *lam_out)
+{
+    int idx[ORC_MAXN], m = 0;
+    for (int i = 0; i < n; ++i)
+        if (S >> i & 1u) idx[m++] = i;
+    double c[ORC_MAXN], one_c = 0.0, one_xu = 0.0;
+    for (int i = 0; i < n; ++i) {
+        c[i] = 0.0;
+        for (int j = 0; j < n; ++j) c[i] += Cdd[i * n + j];
+        one_c += c[i];
+        one_xu += xu[i];
+    }
+    int dim = m + (closed ? 1 : 0);
+    double M[ORC_MAXS * ORC_MAXS], b[ORC_MAXS], z[ORC_MAXS];
+    for (int a = 0; a < m; ++a) {
+        for (int bb = 0; bb < m; ++bb) M[a * dim + bb] = Cdd[idx[a] * n + idx[bb]];
+        if (closed) M[a * dim + m] = c[idx[a]];
+        b[a] = -xu[idx[a]];
+    }
+    if (closed) {
+        for (int bb = 0; bb < m; ++bb) M[m * dim + bb] = c[idx[bb]];
+        M[m * dim + m] = one_c;
+        b[m] = (double)nhat - one_xu;
+    }
+    if (dim > 0 && gauss_solve(dim, M, b, z)) return -1;
+    double mu[ORC_MAXN] = {0};
+    for (int a = 0; a < m; ++a) mu[idx[a]] = z[a];
+    double lam = closed ? z[m] : 0.0;
+    for (int i = 0; i < n; ++i) {
+        double s = xu[i] + lam * c[i];
+        for (int a = 0; a < m; ++a) s += Cdd[i * n + idx[a]] * z[a];
+        x[i] = s;
+    }
+    for (int a = 0; a < m; ++a) x[idx[a]] = 0.0;
+    if (mu_out) memcpy(mu_out, mu, sizeof(double) * n);
+    if (lam_out) *lam_out = lam;
+    return 0;
+}
+
+/* Exact QP by enumeration of active sets in order of increasing size.
+ * Returns the number of the accepted set's elements, or -1 (N <= 16). */
+int orc_qp_enum(int n, const double *Cdd, const double *xu, int closed, int nhat, double *x)
+{
+    if (closed && nhat == 0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        return n;
+    }
+    double scale = 1.0;
+    for (int i = 0; i < n; ++i) scale = fmax(scale, fabs(xu[i]));
+    const double tol = 1e-11 * scale;
+    int maxsize = closed ? n - 1 : n;
+    for (int size = 0; size <= maxsize; ++size) {
+        for (uint32_t S = 0; S < (1u << n); ++S) {
+            if (__builtin_popcount(S) != size) continue;
+            double mu[ORC_MAXN], lam, xx[ORC_MAXN];
+            if (kkt_for_set(n, Cdd, xu, closed, nhat, S, xx, mu, &lam)) continue;
+            int ok = 1;
+            for (int i = 0; i < n && ok; ++i) {
+                if (S >> i & 1u) ok = mu[i] >= -tol;
+                else ok = xx[i] >= -tol;
+            }
+            if (ok) {
+                for (int i = 0; i < n; ++i) x[i] = (S >> i & 1u) ? 0.0 : fmax(xx[i], 0.0);
+                return size;
+            }
+        }
+    }
+    return -1;
+}
+
+/* Exact open QP via Chandrasekaran's method for linear complementarity
+ * problems with a Z-matrix that is positive definite (R. Chandrasekaran,
+ * "A special case of the complementary pivot problem", Opsearch 7, 1970).
+ * In KKT form the open QP is the LCP  w = x_u + C_dd mu >= 0, mu >= 0,
+ * mu^T w = 0 with x = w; the Maxwell C_dd is such a matrix (off-diagonal
+ * entries are minus couplings, App. B proves it positive definite).  Starting
+ * from S = {i : x_u,i < 0}, solve on S and add every index whose x turns
+ * negative; the active set only grows, so at most N rounds.
+ * Returns the number of rounds, or -1. */
+int orc_qp_open_chandrasekaran(int n, const double *Cdd, const double *xu, double *x)
+{
+    uint32_t S = 0;
+    for (int i = 0; i < n; ++i)
+        if (xu[i] < 0.0) S |= 1u << i;
+    for (int round = 1; round <= n + 1; ++round) {
+        if (kkt_for_set(n, Cdd, xu, 0, 0, S, x, NULL, NULL)) return -1;
+        uint32_t add = 0;
+        for (int i = 0; i < n; ++i)
+            if (!(S >> i & 1u) && x[i] < 0.0) add |= 1u << i;
+        if (!add) return round;
+        S |= add;
+    }
+    return -1;
+}
+
+/* Constrained continuous minimum of Sec. 3.1: the analytic solution if it
+ * is non-negative, otherwise the exact QP.  *path = 0 analytic, 1 QP.
+ * Returns 0, or -1 on failure. */
+int orc_cont_min(int n, const double *Cdd, const double *xu, int closed, int nhat,
+                 double *x, int *path)
+{
+    analytic_min(n, Cdd, xu, closed, nhat, x);
+    int ok = 1;
+    for (int i = 0; i < n; ++i) ok &= x[i] >= 0.0;
+    if (ok) { if (path) *path = 0; return 0; }
+    if (path) *path = 1;
+    if (!closed) return orc_qp_open_chandrasekaran(n, Cdd, xu, x) < 0 ? -1 : 0;
+    return orc_qp_enum(n, Cdd, xu, closed, nhat, x) < 0 ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* candidate sets of the method (Sec. 3.2)                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Base point n0, free-dot mask and required number k of raised free dots
+ * (closed arrays; -1 for open).  The candidates are n0 + 1_s for every
+ * s within the free mask (with |s| = k when closed).
+ * Default algorithm (t >= 1): n0 = floor(x*), every dot free (R1).
+ * Thresholded (t < 1): dot i free iff |frac(x*_i) - 1/2| <= t/2; a dot that
+ * is not free is rounded to nearest (R2).  Closed arrays without an
+ * admissible candidate double t (R3).  Returns the threshold used. */
+double orc_candidates(int n, const double *x, int closed, int nhat, double t,
+                      int *n0, uint32_t *freemask, int *k)
+{
+    for (;;) {
+        uint32_t fm = 0;
+        int sum0 = 0;
+        for (int i = 0; i < n; ++i) {
+            double f = floor(x[i]);
+            double frac = x[i] - f;
+            int fi = (int)f;
+            if (t >= 1.0 || fabs(frac - 0.5) <= 0.5 * t) {
+                fm |= 1u << i;
+                n0[i] = fi;
+            } else {
+                n0[i] = fi + (frac > 0.5 ? 1 : 0);
+            }
+            sum0 += n0[i];
+        }
+        *freemask = fm;
+        if (!closed) { *k = -1; return t; }
+        int need = nhat - sum0;
+        if (need >= 0 && need <= __builtin_popcount(fm)) { *k = need; return t; }
+        if (t >= 1.0) { *k = need; return t; } /* cannot happen for |sum x - N_hat| < 1 */
+        t = (t > 0.0) ? fmin(1.0, 2.0 * t) : 1.0;
+    }
+}
+
+/* 1 when a perturbation of x* by 1e-9 could change the candidate set, so
+ * that a floating-point implementation may legitimately score a different
+ * set: floor flips, or the threshold test flips. */
+static int candidates_ambiguous(int n, const double *x, double t)
+{
+    const double eps = 1e-9;
+    for (int i = 0; i < n; ++i) {
+        if (x[i] > eps && fabs(x[i] - nearbyint(x[i])) < eps) return 1;
+        if (t < 1.0) {
+            double frac = x[i] - floor(x[i]);
+            if (fabs(fabs(frac - 0.5) - 0.5 * t) < eps) return 1;
+        }
+    }
+    return 0;
+}
+
+/* Enumerate the candidate set; calls fn(ctx, q) for every candidate. */
+typedef void (*cand_fn)(void *ctx, const int *q);
+
+static void for_each_candidate(int n, const int *n0, uint32_t fm, int k, cand_fn fn, void *ctx)
+{
+    int q[ORC_MAXN];
+    for (uint32_t s = 0; s < (1u << n); ++s) {
+        if (s & ~fm) continue;
+        if (k >= 0 && __builtin_popcount(s) != k) continue;
+        for (int i = 0; i < n; ++i) q[i] = n0[i] + (int)(s >> i & 1u);
+        fn(ctx, q);
+    }
+}
+
+typedef struct {
+    int n;
+    const double *A, *xu;
+    top2_t top;
+} gs_ctx;
+
+static void gs_visit(void *vctx, const int *q)
+{
+    gs_ctx *c = (gs_ctx *)vctx;
+    top2_push(&c->top, energy_i(c->n, c->A, c->xu, q), q);
+}
+
+/* info bits per pixel */
+#define ORC_INFO_QP 1
+#define ORC_INFO_AMBIGUOUS 2
+#define ORC_INFO_DOUBLED 4
+#define ORC_INFO_FAIL 8
+
+/* O-method at T = 0: ground state of every pixel by the paper's algorithm.
+ * Outputs (all per pixel): nstar (P x n), e1 = U(n*), e2 = runner-up energy
+ * within the candidate set (INFINITY when the set has one element),
+ * ncand = number of candidates scored, info bits.  Returns the number of
+ * failed pixels. */
+int64_t orc_method_gs(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                      const double *V, int closed, int nhat, double t,
+                      int *nstar, double *e1, double *e2, int64_t *ncand, int *info)
+{
+    double A[ORC_MAXN * ORC_MAXN];
+    if (orc_inverse(n, Cdd, A)) return P;
+    int64_t fails = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : fails)
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN], x[ORC_MAXN];
+        int path = 0, inf = 0;
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        if (orc_cont_min(n, Cdd, xu, closed, nhat, x, &path)) inf |= ORC_INFO_FAIL;
+        if (path) inf |= ORC_INFO_QP;
+        int n0[ORC_MAXN], k;
+        uint32_t fm;
+        double tu = orc_candidates(n, x, closed, nhat, t, n0, &fm, &k);
+        if (tu != t) inf |= ORC_INFO_DOUBLED;
+        if (candidates_ambiguous(n, x, t)) inf |= ORC_INFO_AMBIGUOUS;
+        gs_ctx c;
+        c.n = n; c.A = A; c.xu = xu;
+        top2_init(&c.top, n);
+        for_each_candidate(n, n0, fm, k, gs_visit, &c);
+        if (c.top.count == 0) inf |= ORC_INFO_FAIL;
+        for (int i = 0; i < n; ++i) nstar[p * n + i] = c.top.q1[i];
+        if (e1) e1[p] = c.top.e1;
+        if (e2) e2[p] = c.top.e2;
+        if (ncand) ncand[p] = c.top.count;
+        if (info) info[p] = inf;
+        if (inf & ORC_INFO_FAIL) fails++;
+    }
+    return fails;
+}
+
+/* Per-pixel continuous minimum and candidate description (for tests and for
+ * the fixed-set softargmin used by finite differences). */
+int64_t orc_method_setup(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                         const double *V, int closed, int nhat, double t,
+                         double *xstar, int *n0, uint32_t *freemask, int *k, int *info)
+{
+    int64_t fails = 0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : fails)
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN], x[ORC_MAXN];
+        int path = 0, inf = 0;
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        if (orc_cont_min(n, Cdd, xu, closed, nhat, x, &path)) inf |= ORC_INFO_FAIL;
+        if (path) inf |= ORC_INFO_QP;
+        double tu = orc_candidates(n, x, closed, nhat, t, n0 + p * n, freemask + p, k + p);
+        if (tu != t) inf |= ORC_INFO_DOUBLED;
+        if (candidates_ambiguous(n, x, t)) inf |= ORC_INFO_AMBIGUOUS;
+        if (xstar) memcpy(xstar + p * n, x, sizeof(double) * n);
+        if (info) info[p] = inf;
+        if (inf & ORC_INFO_FAIL) fails++;
+    }
+    return fails;
+}
+
+/* ---------------------------------------------------------------------- */
+/* softargmin (Sec. 4.2, Eq. softargmin) over the method's candidate set     */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int n;
+    const double *A, *xu;
+    double emin;
+    int pass;
+    double Z, s[ORC_MAXN];
+} soft_ctx;
+
+static double g_kT; /* set per call; read-only inside parallel regions */
+
+static void soft_visit(void *vctx, const int *q)
+{
+    soft_ctx *c = (soft_ctx *)vctx;
+    double e = energy_i(c->n, c->A, c->xu, q);
+    if (c->pass == 0) {
+        if (e < c->emin) c->emin = e;
+        return;
+    }
+    double w = exp(-(e - c->emin) / g_kT);
+    c->Z += w;
+    for (int i = 0; i < c->n; ++i) c->s[i] += w * q[i];
+}
+
+/* softargmin with the candidate sets given per pixel (n0, freemask, k).
+ * Outputs nbar (P x n), emin and logZ = log sum exp(-(E - emin)/kT). */
+void orc_soft_fixed(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                    const double *V, double kT, const int *n0, const uint32_t *freemask,
+                    const int *k, double *nbar, double *emin, double *logZ)
+{
+    double A[ORC_MAXN * ORC_MAXN];
+    if (orc_inverse(n, Cdd, A)) return;
+    g_kT = kT;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN];
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        soft_ctx c;
+        memset(&c, 0, sizeof c);
+        c.n = n; c.A = A; c.xu = xu; c.emin = INFINITY;
+        c.pass = 0;
+        for_each_candidate(n, n0 + p * n, freemask[p], k[p], soft_visit, &c);
+        c.pass = 1;
+        for_each_candidate(n, n0 + p * n, freemask[p], k[p], soft_visit, &c);
+        for (int i = 0; i < n; ++i) nbar[p * n + i] = c.s[i] / c.Z;
+        if (emin) emin[p] = c.emin;
+        if (logZ) logZ[p] = log(c.Z);
+    }
+}
+
+/* O-method at kT > 0: continuous minimum, candidate set, softargmin. */
+int64_t orc_method_soft(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                        const double *V, int closed, int nhat, double t, double kT,
+                        double *nbar, double *emin, double *logZ)
+{
+    int *n0 = (int *)malloc(sizeof(int) * (size_t)(P * n));
+    uint32_t *fm = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)P);
+    int *k = (int *)malloc(sizeof(int) * (size_t)P);
+    int64_t fails = orc_method_setup(P, n, g, Cdd, Cgd, V, closed, nhat, t, NULL, n0, fm, k, NULL);
+    orc_soft_fixed(P, n, g, Cdd, Cgd, V, kT, n0, fm, k, nbar, emin, logZ);
+    free(n0); free(fm); free(k);
+    return fails;
+}
+
+/* ---------------------------------------------------------------------- */
+/* analytic adjoint of the softargmin over fixed candidate sets             */
+/* ---------------------------------------------------------------------- */
+
+/* Given Gbar_p = dL/d nbar_p, returns dL/dC_dd (n x n, every entry an
+ * independent variable), dL/dC_gd (n x g) and dL/dV (P x g).
+ * With pi_s the Boltzmann weight of candidate q_s, d_s = q_s - x_u and
+ * E_s = 1/2 d_s^T A d_s:
+ *   dL/dE_s = -(pi_s / kT) Gbar^T (q_s - nbar)
+ *   dL/dA   = sum_{p,s} dL/dE_s * 1/2 d_s d_s^T
+ *   dL/dx_u = -A sum_s dL/dE_s d_s
+ *   dL/dC_dd = -A (dL/dA) A,  dL/dC_gd = sum_p dL/dx_u,p V_p^T,
+ *   dL/dV_p  = C_gd^T dL/dx_u,p.
+ * Written straight from the chain rule; no reuse of intermediate sums. */
+typedef struct {
+    int n;
+    const double *A, *xu, *gb;
+    double emin, Z, nb[ORC_MAXN];
+    double dA[ORC_MAXN * ORC_MAXN], dxu[ORC_MAXN];
+    int pass;
+} grad_ctx;
+
+static void grad_visit(void *vctx, const int *q)
+{
+    grad_ctx *c = (grad_ctx *)vctx;
+    int n = c->n;
+    double e = energy_i(n, c->A, c->xu, q);
+    if (c->pass == 0) { if (e < c->emin) c->emin = e; return; }
+    double w = exp(-(e - c->emin) / g_kT);
+    if (c->pass == 1) {
+        c->Z += w;
+        for (int i = 0; i < n; ++i) c->nb[i] += w * q[i];
+        return;
+    }
+    double pi = w / c->Z, proj = 0.0;
+    for (int i = 0; i < n; ++i) proj += c->gb[i] * ((double)q[i] - c->nb[i]);
+    double dE = -(pi / g_kT) * proj;
+    double d[ORC_MAXN];
+    for (int i = 0; i < n; ++i) d[i] = (double)q[i] - c->xu[i];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) c->dA[i * n + j] += dE * 0.5 * d[i] * d[j];
+    for (int i = 0; i < n; ++i) {
+        double ad = 0.0;
+        for (int j = 0; j < n; ++j) ad += c->A[i * n + j] * d[j];
+        c->dxu[i] -= dE * ad;
+    }
+}
+
+void orc_soft_grad(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                   const double *V, double kT, const int *n0, const uint32_t *freemask,
+                   const int *k, const double *Gbar, double *dCdd, double *dCgd, double *dV)
+{
+    double A[ORC_MAXN * ORC_MAXN];
+    if (orc_inverse(n, Cdd, A)) return;
+    g_kT = kT;
+    double dA[ORC_MAXN * ORC_MAXN];
+    memset(dA, 0, sizeof dA);
+    memset(dCgd, 0, sizeof(double) * n * g);
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN];
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        grad_ctx c;
+        memset(&c, 0, sizeof c);
+        c.n = n; c.A = A; c.xu = xu; c.gb = Gbar + p * n; c.emin = INFINITY;
+        for (c.pass = 0; c.pass < 3; ++c.pass) {
+            for_each_candidate(n, n0 + p * n, freemask[p], k[p], grad_visit, &c);
+            if (c.pass == 1)
+                for (int i = 0; i < n; ++i) c.nb[i] /= c.Z;
+        }
+        for (int i = 0; i < n * n; ++i) dA[i] += c.dA[i];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < g; ++j) dCgd[i * g + j] += c.dxu[i] * V[p * g + j];
+        for (int j = 0; j < g; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += Cgd[i * g + j] * c.dxu[i];
+            dV[p * g + j] = s;
+        }
+    }
+    /* dL/dC = -A^T (dL/dA) A^T, A symmetric */
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) s += A[a * n + i] * dA[a * n + b] * A[j * n + b];
+            dCdd[i * n + j] = -s;
+        }
+}
+
+/* ---------------------------------------------------------------------- */
+/* O-exact: the definition (Eq. argmin / Eq. softargmin over all admissible) */
+/* ---------------------------------------------------------------------- */
+
+/* An admissible starting state that does not use the method: open, round
+ * x_u and clip at 0; closed, round the clipped closed analytic minimum with
+ * the largest-remainder rule so that the sum is N_hat. */
+static void admissible_point(int n, const double *Cdd, const double *xu, int closed, int nhat,
+                             int *q)
+{
+    if (!closed) {
+        for (int i = 0; i < n; ++i) q[i] = (int)fmax(0.0, nearbyint(xu[i]));
+        return;
+    }
+    double x[ORC_MAXN], rem[ORC_MAXN];
+    analytic_min(n, Cdd, xu, 1, nhat, x);
+    int sum = 0;
+    for (int i = 0; i < n; ++i) {
+        double v = fmax(0.0, x[i]);
+        q[i] = (int)floor(v);
+        rem[i] = v - q[i];
+        sum += q[i];
+    }
+    while (sum > nhat) { /* remove from the largest entries */
+        int b = 0;
+        for (int i = 1; i < n; ++i) if (q[i] > q[b]) b = i;
+        q[b]--; sum--;
+    }
+    while (sum < nhat) { /* add to the largest remainders */
+        int b = 0;
+        for (int i = 1; i < n; ++i) if (rem[i] > rem[b]) b = i;
+        q[b]++; rem[b] = -1.0; sum++;
+        int any = 0;
+        for (int i = 0; i < n; ++i) any |= rem[i] >= 0.0;
+        if (!any) for (int i = 0; i < n; ++i) rem[i] = 0.0;
+    }
+}
+
+/* A second admissible state distinct from q (returns 0 if none exists). */
+static int second_admissible(int n, int closed, const int *q, int *q2)
+{
+    memcpy(q2, q, sizeof(int) * n);
+    if (!closed) { q2[0] += 1; return 1; }
+    if (n < 2) return 0;
+    for (int a = 0; a < n; ++a)
+        if (q[a] > 0) { q2[a]--; q2[(a + 1) % n]++; return 1; }
+    return 0;
+}
+
+/* Certified box: every admissible q with U(q) <= U_ub lies in
+ * |q_i - x_u,i| <= sqrt(2 U_ub (A^{-1})_ii) = sqrt(2 U_ub C_dd,ii), the
+ * extent of the ellipsoid y^T A y <= 2 U_ub along axis i.  U_ub is the
+ * larger energy of two distinct admissible states, so the box holds both the
+ * minimiser and the runner-up.  Brute force over the box (small N only). */
+int64_t orc_exact_box(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                      const double *V, int closed, int nhat, int *nstar, double *e1,
+                      double *e2, int64_t *boxsize)
+{
+    double A[ORC_MAXN * ORC_MAXN];
+    if (orc_inverse(n, Cdd, A)) return P;
+    int64_t fails = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : fails)
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN];
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        int qa[ORC_MAXN], qb[ORC_MAXN];
+        admissible_point(n, Cdd, xu, closed, nhat, qa);
+        double ub = energy_i(n, A, xu, qa);
+        if (second_admissible(n, closed, qa, qb)) ub = fmax(ub, energy_i(n, A, xu, qb));
+        int lo[ORC_MAXN], hi[ORC_MAXN];
+        int64_t size = 1;
+        for (int i = 0; i < n; ++i) {
+            double r = sqrt(2.0 * ub * Cdd[i * n + i]) * (1.0 + 1e-12) + 1e-12;
+            lo[i] = (int)fmax(0.0, ceil(xu[i] - r));
+            hi[i] = (int)floor(xu[i] + r);
+            if (closed && hi[i] > nhat) hi[i] = nhat;
+            if (hi[i] < lo[i]) hi[i] = lo[i] - 1;
+            size *= (int64_t)(hi[i] - lo[i] + 1);
+        }
+        top2_t top;
+        top2_init(&top, n);
+        if (size > 0) {
+            int q[ORC_MAXN];
+            for (int i = 0; i < n; ++i) q[i] = lo[i];
+            for (;;) {
+                int ok = 1;
+                if (closed) {
+                    int s = 0;
+                    for (int i = 0; i < n; ++i) s += q[i];
+                    ok = s == nhat;
+                }
+                if (ok) top2_push(&top, energy_i(n, A, xu, q), q);
+                int i = n - 1;
+                while (i >= 0 && q[i] == hi[i]) { q[i] = lo[i]; --i; }
+                if (i < 0) break;
+                q[i]++;
+            }
+        }
+        if (top.count == 0) fails++;
+        for (int i = 0; i < n; ++i) nstar[p * n + i] = top.q1[i];
+        if (e1) e1[p] = top.e1;
+        if (e2) e2[p] = top.e2;
+        if (boxsize) boxsize[p] = size;
+    }
+    return fails;
+}
+
+/* Closed arrays: every composition of N_hat into n non-negative parts. */
+int64_t orc_exact_compositions(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                               const double *V, int nhat, int *nstar, double *e1, double *e2)
+{
+    double A[ORC_MAXN * ORC_MAXN];
+    if (orc_inverse(n, Cdd, A)) return P;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN];
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        top2_t top;
+        top2_init(&top, n);
+        int q[ORC_MAXN];
+        for (int i = 0; i < n; ++i) q[i] = 0;
+        q[n - 1] = nhat;
+        /* odometer over q_0..q_{n-2} in [0, nhat], last entry takes the rest */
+        for (;;) {
+            int s = 0;
+            for (int i = 0; i < n - 1; ++i) s += q[i];
+            if (s <= nhat) {
+                q[n - 1] = nhat - s;
+                top2_push(&top, energy_i(n, A, xu, q), q);
+            }
+            int i = n - 2;
+            while (i >= 0 && q[i] == nhat) { q[i] = 0; --i; }
+            if (i < 0) break;
+            q[i]++;
+        }
+        for (int i = 0; i < n; ++i) nstar[p * n + i] = top.q1[i];
+        if (e1) e1[p] = top.e1;
+        if (e2) e2[p] = top.e2;
+    }
+    return 0;
+}
+
+/* Schnorr-Euchner depth-first enumeration (C. P. Schnorr and M. Euchner,
+ * Math. Programming 66, 1994; E. Agrell et al., IEEE Trans. IT 48, 2002)
+ * of 2 U(q) = || R (q - x_u) ||^2 with A = R^T R, R upper triangular:
+ *   2 U = sum_k R_kk^2 (q_k - c_k)^2,
+ *   c_k = x_u,k - sum_{j>k} (R_kj / R_kk) (q_j - x_u,j).
+ * Levels run from k = n-1 down to 0, values at each level in zig-zag order
+ * around c_k; q_k >= 0 is enforced, and for closed arrays the partial sum may
+ * not exceed N_hat and q_0 takes the remainder. */
+typedef struct {
+    int n, closed, nhat;
+    const double *R, *xu;
+    double r2;      /* current squared radius (2 U) */
+    int shrink;     /* 1: T = 0 search (radius = 2 * runner-up energy) */
+    int q[ORC_MAXN];
+    top2_t top;
+    /* soft accumulation */
+    double kT, eref, Z, s[ORC_MAXN];
+    int64_t nodes;
+} se_ctx;
+
+static void se_leaf(se_ctx *c, double cost)
+{
+    double e = 0.5 * cost;
+    if (c->shrink) {
+        top2_push(&c->top, e, c->q);
+        if (c->top.e2 < INFINITY) c->r2 = 2.0 * c->top.e2 * (1.0 + 1e-12) + 1e-300;
+    } else {
+        double w = exp(-(e - c->eref) / c->kT);
+        c->Z += w;
+        for (int i = 0; i < c->n; ++i) c->s[i] += w * c->q[i];
+        c->top.count++;
+    }
+}
+
+static void se_level(se_ctx *c, int k, double partial, int used)
+{
+    c->nodes++;
+    const int n = c->n;
+    const double *R = c->R;
+    double ck = c->xu[k];
+    for (int j = k + 1; j < n; ++j) ck -= R[k * n + j] / R[k * n + k] * ((double)c->q[j] - c->xu[j]);
+    const double rkk2 = R[k * n + k] * R[k * n + k];
+    if (c->closed && k == 0) {
+        int v = c->nhat - used;
+        if (v < 0) return;
+        double cost = partial + rkk2 * ((double)v - ck) * ((double)v - ck);
+        if (cost <= c->r2) { c->q[0] = v; se_leaf(c, cost); }
+        return;
+    }
+    int vmax = c->closed ? c->nhat - used : INT32_MAX;
+    int start = (int)nearbyint(ck);
+    if (start < 0) start = 0;
+    if (start > vmax) start = vmax;
+    /* walk up from start and down from start - 1, nearest first */
+    int up = start, dn = start - 1, up_alive = 1, dn_alive = dn >= 0;
+    while (up_alive || dn_alive) {
+        int v;
+        double du = up_alive ? fabs((double)up - ck) : INFINITY;
+        double dd = dn_alive ? fabs((double)dn - ck) : INFINITY;
+        if (du <= dd) v = up; else v = dn;
+        double cost = partial + rkk2 * ((double)v - ck) * ((double)v - ck);
+        if (cost > c->r2) {
+            /* the distance only grows along this direction */
+            if (v == up) up_alive = 0; else dn_alive = 0;
+            continue;
+        }
+        c->q[k] = v;
+        if (k == 0) se_leaf(c, cost);
+        else se_level(c, k - 1, cost, used + v);
+        if (v == up) { up++; if (up > vmax) up_alive = 0; }
+        else { dn--; if (dn < 0) dn_alive = 0; }
+    }
+}
+
+static int se_prepare(int n, const double *Cdd, double *A, double *R)
+{
+    if (orc_inverse(n, Cdd, A)) return -1;
+    return cholesky_upper(n, A, R);
+}
+
+int64_t orc_exact_se(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                     const double *V, int closed, int nhat, int *nstar, double *e1, double *e2,
+                     int64_t *nodes)
+{
+    double A[ORC_MAXN * ORC_MAXN], R[ORC_MAXN * ORC_MAXN];
+    if (se_prepare(n, Cdd, A, R)) return P;
+    int64_t fails = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : fails)
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN];
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        se_ctx c;
+        memset(&c, 0, sizeof c);
+        c.n = n; c.closed = closed; c.nhat = nhat; c.R = R; c.xu = xu;
+        c.r2 = INFINITY; c.shrink = 1;
+        top2_init(&c.top, n);
+        se_level(&c, n - 1, 0.0, 0);
+        if (c.top.count == 0) fails++;
+        for (int i = 0; i < n; ++i) nstar[p * n + i] = c.top.q1[i];
+        if (e1) e1[p] = c.top.e1;
+        if (e2) e2[p] = c.top.e2;
+        if (nodes) nodes[p] = c.nodes;
+    }
+    return fails;
+}
+
+/* Softargmin over every admissible state with U <= U_min + 40 kT (the mass
+ * left out is below count * e^-40).  Outputs nbar and the number of states. */
+int64_t orc_exact_soft(int64_t P, int n, int g, const double *Cdd, const double *Cgd,
+                       const double *V, int closed, int nhat, double kT, double *nbar,
+                       int64_t *nstates)
+{
+    double A[ORC_MAXN * ORC_MAXN], R[ORC_MAXN * ORC_MAXN];
+    if (se_prepare(n, Cdd, A, R)) return P;
+    int64_t fails = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : fails)
+    for (int64_t p = 0; p < P; ++p) {
+        double xu[ORC_MAXN];
+        pixel_xu(n, g, Cgd, V + p * g, xu);
+        se_ctx c;
+        memset(&c, 0, sizeof c);
+        c.n = n; c.closed = closed; c.nhat = nhat; c.R = R; c.xu = xu;
+        c.r2 = INFINITY; c.shrink = 1;
+        top2_init(&c.top, n);
+        se_level(&c, n - 1, 0.0, 0);
+        if (c.top.count == 0) { fails++; continue; }
+        double umin = c.top.e1;
+        memset(&c, 0, sizeof c);
+        c.n = n; c.closed = closed; c.nhat = nhat; c.R = R; c.xu = xu;
+        c.r2 = 2.0 * (umin + 40.0 * kT) * (1.0 + 1e-12);
+        c.shrink = 0; c.kT = kT; c.eref = umin;
+        top2_init(&c.top, n);
+        se_level(&c, n - 1, 0.0, 0);
+        for (int i = 0; i < n; ++i) nbar[p * n + i] = c.s[i] / c.Z;
+        if (nstates) nstates[p] = c.top.count;
+    }
+    return fails;
+}
+
+void orc_set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
