@@ -33,8 +33,11 @@
  *
  * Readings where the paper is silent or ambiguous (each is listed in the
  * design notes of the repository):
- *   R1 floor/ceil box = f + {0,1}^N with f = floor(x*), also when x*_i is an
- *      exact integer (Sec. 3.2.1 does not say what happens then).
+ *   R1 floor/ceil box = f + {0,1}^N with f = floor(x* + 1e-9): a continuous
+ *      minimum that sits on an integer (an active bound x_i = 0, or a closed
+ *      array whose free dot holds a whole charge) starts its box at that
+ *      integer however the last bit of x* was rounded.  Sec. 3.2.1 does not
+ *      say what floor and ceil give at an exact integer.
  *   R2 thresholded: dot i is "free" when |frac(x*_i) - 1/2| <= t/2 (inclusive),
  *      other dots are rounded to nearest (Sec. 3.2.2).
  *   R3 closed arrays with no admissible thresholded candidate double t for
@@ -57,6 +60,7 @@
 
 #define ORC_MAXN 16
 #define ORC_MAXS (ORC_MAXN + 1)
+#define ORC_FLOOR_EPS 1e-9 /* reading R1 */
 
 /* ---------------------------------------------------------------------- */
 /* small dense linear algebra                                              */
@@ -367,7 +371,7 @@ double orc_candidates(int n, const double *x, int closed, int nhat, double t,
         uint32_t fm = 0;
         int sum0 = 0;
         for (int i = 0; i < n; ++i) {
-            double f = floor(x[i]);
+            double f = floor(x[i] + ORC_FLOOR_EPS);
             double frac = x[i] - f;
             int fi = (int)f;
             if (t >= 1.0 || fabs(frac - 0.5) <= 0.5 * t) {
@@ -387,16 +391,17 @@ double orc_candidates(int n, const double *x, int closed, int nhat, double t,
     }
 }
 
-/* 1 when a perturbation of x* by 1e-9 could change the candidate set, so
+/* 1 when a perturbation of x* by 1e-11 could change the candidate set, so
  * that a floating-point implementation may legitimately score a different
- * set: floor flips, or the threshold test flips. */
+ * set: the shifted floor flips, or the threshold test flips. */
 static int candidates_ambiguous(int n, const double *x, double t)
 {
-    const double eps = 1e-9;
+    const double eps = 1e-11;
     for (int i = 0; i < n; ++i) {
-        if (x[i] > eps && fabs(x[i] - nearbyint(x[i])) < eps) return 1;
+        double y = x[i] + ORC_FLOOR_EPS;
+        if (fabs(y - nearbyint(y)) < eps) return 1;
         if (t < 1.0) {
-            double frac = x[i] - floor(x[i]);
+            double frac = x[i] - floor(y);
             if (fabs(fabs(frac - 0.5) - 0.5 * t) < eps) return 1;
         }
     }
