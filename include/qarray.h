@@ -1,0 +1,205 @@
+/*
+ * qarray.h -- C ABI of the MI355X constant-capacitance ground-state library
+ * (libqarray.so, hand-written HIP for gfx950).
+ *
+ * The problem is the one stated in van Straaten et al., "QArray: a
+ * GPU-accelerated constant capacitance model simulator for large quantum dot
+ * arrays" (arXiv 2404.04994):
+ *
+ *   For every pixel p (a vector V_p of gate voltages), with A = C_dd^{-1} and
+ *   x_u = C_gd V_p (the open continuous minimum, Sec. 3.1.1), find the dot
+ *   charge vector n that minimises the free energy (Sec. 2, Eq. free_energy)
+ *       U(n) = 1/2 (n - x_u)^T A (n - x_u)
+ *   over integer n >= 0 (open array), additionally with sum(n) = N_hat
+ *   (closed array, constraint iii of Sec. 2).  The library implements the
+ *   paper's two-stage method (Sec. 3): the constrained continuous minimum x*
+ *   (analytic solution of Sec. 3.1.1 / App. C-D, else the QP of Sec. 3.1.2),
+ *   then the candidate states around it -- the 2^N floor/ceil box of
+ *   Sec. 3.2.1 (threshold t = 1) or the thresholded subset of Sec. 3.2.2
+ *   (t < 1, closed arrays double t when no admissible state is left) -- and
+ *   finally the argmin (Eq. argmin, T = 0) or the Boltzmann softargmin
+ *   (Sec. 4.2, Eq. softargmin, kT > 0) over those candidates.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: e = 1, so kT is in the energy units of U (Sec. 6).  Charges are
+ *   holes as written in Sec. 2; for electrons pass -V (U is invariant under
+ *   n -> -n, V -> -V up to a constant).
+ * Layout: all matrices are row-major FP64.  V is P x G, one row per pixel.
+ *   Outputs are P x N, one row per pixel.
+ * Candidate set: f = floor(x*), the candidates are f + b with b in {0,1}^N
+ *   (also when x*_i is an exact integer); thresholded dots with
+ *   |frac(x*_i) - 1/2| > t/2 are rounded to nearest instead; ties in energy
+ *   resolve to the lexicographically smallest n (dot 0 most significant).
+ * Memory: every buffer is owned by the caller.  "_dev" arguments are device
+ *   pointers on the current HIP device; problem matrices are host pointers
+ *   that are read before the call returns.  The library keeps a private
+ *   workspace per (device, stream), grown on demand with hipMalloc and freed
+ *   by qa_release(); it never keeps caller pointers after returning.
+ * Streams: work is enqueued on `hip_stream` (a hipStream_t; NULL = the null
+ *   stream) and the call returns without waiting, unless `stats` is non-NULL,
+ *   in which case the call waits for the stream to copy the counters back.
+ *   Calls on the same stream run in order; concurrent calls on different
+ *   streams use different workspaces.
+ * Errors: every entry point returns a qa_status; nothing is thrown or
+ *   aborted across the ABI.  Validation (FP64, on the host) happens before any
+ *   device work: on error nothing is enqueued and no output is written.
+ *   qa_last_error() describes the last failure on the calling thread.
+ */
+#ifndef QARRAY_H
+#define QARRAY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QA_MAX_DOT 16  /* largest n_dot the kernels are built for */
+#define QA_MAX_GATE 32 /* largest n_gate */
+
+typedef enum {
+    QA_OK = 0,
+    QA_E_NULL = 1,          /* a required pointer is NULL */
+    QA_E_SHAPE = 2,         /* n_dot/n_gate/P out of range */
+    QA_E_NOT_SYMMETRIC = 3, /* C_dd not symmetric to 1e-12 relative */
+    QA_E_NOT_PD = 4,        /* C_dd not positive definite (App. B) */
+    QA_E_RANGE = 5,         /* t not in [0,1], kT < 0 or not finite, N_hat < 0,
+                               non-finite matrix entry, bad enum value */
+    QA_E_UNSUPPORTED = 6,   /* valid input outside what this build handles */
+    QA_E_WORKSPACE = 7,     /* device allocation failed */
+    QA_E_DEVICE = 8         /* a HIP call failed (launch, copy, fault) */
+} qa_status;
+
+typedef enum { QA_OPEN = 0, QA_CLOSED = 1 } qa_mode;
+
+/* Arithmetic used to score the candidate states.
+ *  QA_PREC_FP64   : every candidate energy in FP64 on the vector ALUs.
+ *  QA_PREC_FP32   : b^T g on FP32 matrix cores, FP64 re-score of near ties.
+ *  QA_PREC_BF16X3 : b^T g on BF16 matrix cores with g split exactly into
+ *                   three BF16 parts (FP32 accumulation), FP64 re-score of
+ *                   near ties.
+ *  QA_PREC_BF16X2 : as BF16X3 with two parts (g rounded to 16 significant
+ *                   bits), FP64 re-score of near ties.
+ * The integer result is the same for all four: the near-tie re-score
+ * replaces the approximate argmin by the FP64 one whenever the approximate
+ * runner-up lies within the certified error band.  The matrix-core forms are
+ * used for the dense box (t = 1) of open arrays at T = 0 with n_dot >= 9;
+ * elsewhere the FP64 form runs regardless of the request. */
+typedef enum {
+    QA_PREC_FP64 = 0,
+    QA_PREC_FP32 = 1,
+    QA_PREC_BF16X3 = 2,
+    QA_PREC_BF16X2 = 3
+} qa_precision;
+
+typedef struct {
+    int32_t n_dot;       /* N, 1..QA_MAX_DOT */
+    int32_t n_gate;      /* G, 1..QA_MAX_GATE */
+    const double *cdd;   /* host, N x N Maxwell dot-dot block (Sec. 2):
+                            diagonal = total capacitance, off-diagonal =
+                            minus the coupling; symmetric positive definite */
+    const double *cgd;   /* host, N x G gate-dot coupling (x_u = C_gd V) */
+    int32_t mode;        /* qa_mode */
+    int32_t n_charge;    /* N_hat >= 0 for QA_CLOSED, ignored for QA_OPEN */
+    double kT;           /* >= 0; used by qa_soft_charge* only */
+    double threshold;    /* t in [0,1]; 1 = the default 2^N box */
+    int32_t precision;   /* qa_precision */
+    int32_t reserved;
+} qa_problem;
+
+typedef struct {
+    int64_t pixels;            /* pixels processed */
+    int64_t qp_pixels;         /* analytic minimum infeasible -> QP solved */
+    int64_t qp_failures;       /* QP did not reach a KKT point (should be 0) */
+    int64_t doubled_pixels;    /* closed thresholded pixels whose t doubled */
+    int64_t near_tie_pixels;   /* approximate scoring flagged -> FP64 re-score */
+    int64_t fp64_gap_below_1e9;/* pixels whose FP64 best/runner-up gap < 1e-9 */
+    int64_t candidates;        /* candidate states scored (approximate pass) */
+    int64_t band_overflow;     /* near-tie pixels whose error band held more
+                                  states than the in-kernel re-score keeps;
+                                  they get a full FP64 pass instead */
+} qa_stats;
+
+/* Ground state at T = 0 (Sec. 3, Eq. argmin) of P pixels.
+ *   V_dev     : device, P x G FP64 gate voltages.
+ *   P         : number of pixels, >= 0 (0 is a no-op).
+ *   n_out_dev : device, P x N int32, receives n* per pixel.
+ *   stats     : host, may be NULL (then the call does not wait). */
+qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P,
+                          int32_t *n_out_dev, qa_stats *stats, void *hip_stream);
+
+/* Thermal softargmin (Sec. 4.2, Eq. softargmin) over the candidate set of
+ * each pixel, in FP64.
+ *   nbar_out_dev : device, P x N FP64, receives <n> per pixel.
+ *   saved_dev    : device, qa_saved_bytes(P, N) bytes, or NULL; receives
+ *                  what qa_soft_charge_backward needs (candidate set and
+ *                  normaliser per pixel; the energies are not stored). */
+qa_status qa_soft_charge(const qa_problem *prob, const double *V_dev, int64_t P,
+                         double *nbar_out_dev, void *saved_dev, qa_stats *stats,
+                         void *hip_stream);
+
+/* Adjoint of qa_soft_charge.  Given grad_nbar = dL/d<n> (device, P x N
+ * FP64) and the saved buffer of the forward call with the same problem and
+ * V, writes
+ *   grad_cdd_dev : device, N x N FP64, dL/dC_dd (every entry independent),
+ *   grad_cgd_dev : device, N x G FP64, dL/dC_gd,
+ *   grad_V_dev   : device, P x G FP64, dL/dV, or NULL to skip.
+ * The candidate set is piecewise constant in the inputs, so only the
+ * energies carry gradient; they are recomputed, not read back.  This is not
+ * in the paper (which notes that the discrete model defeats autograd,
+ * Sec. 6); it differentiates the softargmin exactly.  n_dot <= 12. */
+qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, int64_t P,
+                                  const double *grad_nbar_dev, const void *saved_dev,
+                                  double *grad_cdd_dev, double *grad_cgd_dev,
+                                  double *grad_V_dev, void *hip_stream);
+
+/* Bytes of the saved buffer for P pixels of an N-dot problem. */
+size_t qa_saved_bytes(int64_t P, int32_t n_dot);
+
+/* A batch of independent diagrams (the dataset-generation use of Sec. 1)
+ * in one launch sequence.  Diagram d uses probs[d] (its own N, G, mode,
+ * N_hat, kT, t) and the gate voltages V_dev + v_offsets[d] (P_d x G_d,
+ * FP64, P_d = out_offsets[d+1]/N_d - out_offsets[d]/N_d rows ... see below).
+ *   v_offsets   : host, n_diag entries, element offset of diagram d's V.
+ *   pix_counts  : host, n_diag entries, P_d.
+ *   out_offsets : host, n_diag entries, element offset of diagram d's
+ *                 output rows (P_d x N_d) in n_out_dev / nbar_out_dev.
+ *   n_out_dev   : device int32, receives the T = 0 ground state of every
+ *                 diagram (argmin over the candidate set).
+ *   nbar_out_dev: device FP64 or NULL; receives the softargmin of diagrams
+ *                 with kT > 0 (rows of kT = 0 diagrams get n* as FP64).
+ * All diagrams share the precision of probs[0] (FP64 in this build). */
+qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
+                                  const int64_t *v_offsets, const int64_t *pix_counts,
+                                  const int64_t *out_offsets, int32_t *n_out_dev,
+                                  double *nbar_out_dev, qa_stats *stats, void *hip_stream);
+
+/* Stage timing (diagnostics).  While enabled, every ground-state call on a
+ * stream records HIP events on that stream around its three stages:
+ *   stage 0: prologue, continuous minimum and candidate setup,
+ *   stage 1: candidate scoring (the matrix-core or FP64 scorer),
+ *   stage 2: FP64 re-score of near-tie pixels (0 when not used).
+ * qa_timing_reset() forgets earlier records of the stream;
+ * qa_timing_sum() waits for the stream and writes the summed milliseconds
+ * of each stage (ms_out[3]) over the calls recorded since the reset and the
+ * number of calls (at most 4096 are kept).  Off by default. */
+void qa_timing_enable(int on);
+void qa_timing_reset(void *hip_stream);
+qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *qa_last_error(void);
+
+/* Free the library workspace of `hip_stream` on the current device; call
+ * after the stream's work has finished.  Safe to call more than once. */
+void qa_release(void *hip_stream);
+
+/* Library version string. */
+const char *qa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QARRAY_H */

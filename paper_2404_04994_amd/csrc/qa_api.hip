@@ -1,0 +1,393 @@
+// qa_api.hip -- host side of the C ABI declared in include/qarray.h:
+// validation (FP64, before any device work), the per-(device, stream)
+// workspace, and the launch sequence of the ground-state path.
+#include "../../include/qarray.h"
+#include "qa_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <array>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace qa;
+
+namespace {
+
+thread_local std::string g_err;
+
+qa_status fail(qa_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define QA_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(QA_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+struct Workspace {
+    hipStream_t stream = nullptr;
+    DiagRec *dr = nullptr;
+    int64_t dr_cap = 0;
+    PixRec *pr = nullptr;
+    int64_t pr_cap = 0;
+    int32_t *qp_list = nullptr;
+    int64_t qp_cap = 0;
+    int32_t *flag_list = nullptr;
+    int64_t flag_cap = 0;
+    int64_t *counters = nullptr;
+    double *acc = nullptr;
+    int64_t acc_cap = 0;
+    // stage timing: event sets {start, after setup, after scoring, after re-score}
+    std::vector<std::array<hipEvent_t, 4>> ev;
+    int64_t ev_used = 0;
+};
+
+constexpr int64_t kMaxTimedCalls = 4096;
+bool g_timing = false;
+
+// returns the event set of this call, or nullptr when timing is off/full
+std::array<hipEvent_t, 4> *timing_slot(Workspace *w)
+{
+    if (!g_timing || w->ev_used >= kMaxTimedCalls) return nullptr;
+    if (w->ev_used >= (int64_t)w->ev.size()) {
+        std::array<hipEvent_t, 4> e{};
+        for (auto &x : e)
+            if (hipEventCreate(&x) != hipSuccess) return nullptr;
+        w->ev.push_back(e);
+    }
+    return &w->ev[w->ev_used++];
+}
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+
+template <typename T>
+qa_status grow(Workspace *w, T *&ptr, int64_t &cap, int64_t need)
+{
+    if (need <= cap && ptr) return QA_OK;
+    if (ptr) {
+        QA_HIP(hipStreamSynchronize(w->stream));
+        QA_HIP(hipFree(ptr));
+        ptr = nullptr;
+        cap = 0;
+    }
+    int64_t n = need < 1 ? 1 : need;
+    if (hipMalloc((void **)&ptr, sizeof(T) * (size_t)n) != hipSuccess) {
+        ptr = nullptr;
+        return fail(QA_E_WORKSPACE, "hipMalloc of %lld bytes failed",
+                    (long long)(sizeof(T) * (size_t)n));
+    }
+    cap = n;
+    return QA_OK;
+}
+
+qa_status get_ws(hipStream_t stream, Workspace **out)
+{
+    int dev = 0;
+    QA_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it == g_ws.end()) {
+        Workspace *w = new Workspace();
+        w->stream = stream;
+        if (hipMalloc((void **)&w->counters, sizeof(int64_t) * C_NUM) != hipSuccess) {
+            delete w;
+            return fail(QA_E_WORKSPACE, "hipMalloc of the counters failed");
+        }
+        it = g_ws.emplace(key, w).first;
+    }
+    *out = it->second;
+    return QA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation (FP64 on the host, before any device work)
+// ---------------------------------------------------------------------------
+qa_status validate(const qa_problem *pb, bool need_kT)
+{
+    if (!pb) return fail(QA_E_NULL, "problem is NULL");
+    if (pb->n_dot < 1 || pb->n_dot > QA_MAX_DOT)
+        return fail(QA_E_SHAPE, "n_dot=%d outside [1, %d]", pb->n_dot, QA_MAX_DOT);
+    if (pb->n_gate < 1 || pb->n_gate > QA_MAX_GATE)
+        return fail(QA_E_SHAPE, "n_gate=%d outside [1, %d]", pb->n_gate, QA_MAX_GATE);
+    if (!pb->cdd || !pb->cgd) return fail(QA_E_NULL, "cdd or cgd is NULL");
+    const int n = pb->n_dot, g = pb->n_gate;
+    double amax = 0.0;
+    for (int i = 0; i < n * n; ++i) {
+        if (!std::isfinite(pb->cdd[i])) return fail(QA_E_RANGE, "cdd[%d] is not finite", i);
+        amax = std::fmax(amax, std::fabs(pb->cdd[i]));
+    }
+    for (int i = 0; i < n * g; ++i)
+        if (!std::isfinite(pb->cgd[i])) return fail(QA_E_RANGE, "cgd[%d] is not finite", i);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j)
+            if (std::fabs(pb->cdd[i * n + j] - pb->cdd[j * n + i]) > 1e-12 * amax)
+                return fail(QA_E_NOT_SYMMETRIC, "cdd[%d][%d] != cdd[%d][%d]", i, j, j, i);
+    // positive definiteness by Cholesky (App. B: the Maxwell block is PD)
+    double L[QA_MAX_DOT * QA_MAX_DOT] = {0};
+    for (int j = 0; j < n; ++j) {
+        double d = pb->cdd[j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0.0)) return fail(QA_E_NOT_PD, "cdd is not positive definite (pivot %d)", j);
+        L[j * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double s = pb->cdd[i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = s / L[j * n + j];
+        }
+    }
+    if (pb->mode != QA_OPEN && pb->mode != QA_CLOSED)
+        return fail(QA_E_RANGE, "mode=%d is not QA_OPEN or QA_CLOSED", pb->mode);
+    if (pb->mode == QA_CLOSED && (pb->n_charge < 0 || pb->n_charge > 1000000))
+        return fail(QA_E_RANGE, "n_charge=%d outside [0, 1e6]", pb->n_charge);
+    if (!std::isfinite(pb->threshold) || pb->threshold < 0.0 || pb->threshold > 1.0)
+        return fail(QA_E_RANGE, "threshold=%g outside [0, 1]", pb->threshold);
+    if (!std::isfinite(pb->kT) || pb->kT < 0.0)
+        return fail(QA_E_RANGE, "kT=%g is negative or not finite", pb->kT);
+    if (need_kT && !(pb->kT > 0.0))
+        return fail(QA_E_RANGE, "the softargmin needs kT > 0 (got %g)", pb->kT);
+    if (pb->precision < QA_PREC_FP64 || pb->precision > QA_PREC_BF16X2)
+        return fail(QA_E_RANGE, "precision=%d unknown", pb->precision);
+    return QA_OK;
+}
+
+void fill_diag(const qa_problem *pb, DiagRec *h)
+{
+    std::memset(h, 0, sizeof(DiagRec));
+    const int n = pb->n_dot, g = pb->n_gate;
+    h->n = n;
+    h->g = g;
+    h->closed = pb->mode == QA_CLOSED;
+    h->nhat = pb->mode == QA_CLOSED ? pb->n_charge : 0;
+    h->kT = pb->kT;
+    h->t = pb->threshold;
+    h->prec = pb->precision;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) h->Cdd[i * kMaxDot + j] = pb->cdd[i * n + j];
+        for (int j = 0; j < g; ++j) h->Cgd[i * kMaxGate + j] = pb->cgd[i * g + j];
+    }
+}
+
+// prologue + setup + QP for one diagram, shared by the entry points
+qa_status run_setup(Workspace *w, const qa_problem *pb, const double *V, int64_t P)
+{
+    qa_status st;
+    if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
+    if ((st = grow(w, w->pr, w->pr_cap, P))) return st;
+    if ((st = grow(w, w->qp_list, w->qp_cap, P))) return st;
+    if ((st = grow(w, w->flag_list, w->flag_cap, P))) return st;
+    DiagRec h;
+    fill_diag(pb, &h);
+    QA_HIP(launch_zero_i64(w->counters, C_NUM, w->stream));
+    QA_HIP(hipMemcpyAsync(w->dr, &h, sizeof(DiagRec), hipMemcpyHostToDevice, w->stream));
+    QA_HIP(launch_prep(w->dr, 1, w->stream));
+    const bool closed = pb->mode == QA_CLOSED;
+    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, w->stream));
+    QA_HIP(launch_qp(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, w->stream));
+    return QA_OK;
+}
+
+qa_status read_stats(Workspace *w, qa_stats *stats)
+{
+    if (!stats) return QA_OK;
+    int64_t c[C_NUM];
+    QA_HIP(hipMemcpyAsync(c, w->counters, sizeof c, hipMemcpyDeviceToHost, w->stream));
+    QA_HIP(hipStreamSynchronize(w->stream));
+    stats->pixels = c[C_PIXELS];
+    stats->qp_pixels = c[C_QP];
+    stats->qp_failures = c[C_QP_FAIL];
+    stats->doubled_pixels = c[C_DOUBLED];
+    stats->near_tie_pixels = c[C_NEAR_TIE];
+    stats->fp64_gap_below_1e9 = c[C_GAP_1E9];
+    stats->candidates = c[C_CANDIDATES];
+    stats->band_overflow = c[C_BAND_OVERFLOW];
+    return QA_OK;
+}
+
+bool use_matrix_cores(const qa_problem *pb)
+{
+    return pb->precision != QA_PREC_FP64 && pb->threshold >= 1.0 && pb->n_dot >= 9 &&
+           pb->mode == QA_OPEN;
+}
+
+}  // namespace
+
+extern "C" {
+
+qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P,
+                          int32_t *n_out_dev, qa_stats *stats, void *hip_stream)
+{
+    g_err.clear();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
+    if (P == 0) {
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return QA_OK;
+    }
+    if (!V_dev || !n_out_dev) return fail(QA_E_NULL, "V_dev or n_out_dev is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    std::array<hipEvent_t, 4> *ev = timing_slot(w);
+    if (ev) QA_HIP(hipEventRecord((*ev)[0], w->stream));
+    if ((st = run_setup(w, prob, V_dev, P))) return st;
+    if (ev) QA_HIP(hipEventRecord((*ev)[1], w->stream));
+    if (use_matrix_cores(prob)) {
+        QA_HIP(launch_score_mfma(w->dr, w->pr, P, prob->precision, n_out_dev, w->flag_list,
+                                 w->counters, prob->n_dot, w->stream));
+        if (ev) QA_HIP(hipEventRecord((*ev)[2], w->stream));
+        QA_HIP(launch_score_fp64(w->dr, w->pr, P, w->flag_list, w->counters + C_FLAG_LIST,
+                                 n_out_dev, w->counters, prob->n_dot, w->stream));
+    } else {
+        QA_HIP(launch_score_fp64(w->dr, w->pr, P, nullptr, nullptr, n_out_dev, w->counters,
+                                 prob->n_dot, w->stream));
+        if (ev) QA_HIP(hipEventRecord((*ev)[2], w->stream));
+    }
+    if (ev) QA_HIP(hipEventRecord((*ev)[3], w->stream));
+    return read_stats(w, stats);
+}
+
+size_t qa_saved_bytes(int64_t P, int32_t n_dot)
+{
+    (void)n_dot;
+    return P <= 0 ? 0 : (size_t)P * sizeof(SavedRec);
+}
+
+qa_status qa_soft_charge(const qa_problem *prob, const double *V_dev, int64_t P,
+                         double *nbar_out_dev, void *saved_dev, qa_stats *stats, void *hip_stream)
+{
+    g_err.clear();
+    qa_status st = validate(prob, true);
+    if (st) return st;
+    if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
+    if (P == 0) {
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return QA_OK;
+    }
+    if (!V_dev || !nbar_out_dev) return fail(QA_E_NULL, "V_dev or nbar_out_dev is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    if ((st = run_setup(w, prob, V_dev, P))) return st;
+    QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar_out_dev, (SavedRec *)saved_dev, w->counters,
+                           prob->n_dot, w->stream));
+    return read_stats(w, stats);
+}
+
+qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, int64_t P,
+                                  const double *grad_nbar_dev, const void *saved_dev,
+                                  double *grad_cdd_dev, double *grad_cgd_dev, double *grad_V_dev,
+                                  void *hip_stream)
+{
+    g_err.clear();
+    qa_status st = validate(prob, true);
+    if (st) return st;
+    if (prob->n_dot > 12)
+        return fail(QA_E_UNSUPPORTED, "the adjoint is built for n_dot <= 12 (got %d)", prob->n_dot);
+    if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
+    if (!grad_cdd_dev || !grad_cgd_dev) return fail(QA_E_NULL, "gradient output is NULL");
+    if (P > 0 && (!V_dev || !grad_nbar_dev || !saved_dev))
+        return fail(QA_E_NULL, "V_dev, grad_nbar_dev or saved_dev is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
+    const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + 4096;
+    if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
+    DiagRec h;
+    fill_diag(prob, &h);
+    QA_HIP(hipMemcpyAsync(w->dr, &h, sizeof(DiagRec), hipMemcpyHostToDevice, w->stream));
+    QA_HIP(launch_prep(w->dr, 1, w->stream));
+    double *accA = w->acc, *accG = accA + kMaxDot * kMaxDot, *accU = accG + kMaxDot * kMaxGate;
+    QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, accA, accG,
+                           accU, grad_V_dev, prob->n_dot, w->stream));
+    QA_HIP(launch_soft_bwd_final(w->dr, accA, accG, accU, grad_cdd_dev, grad_cgd_dev, w->stream));
+    return QA_OK;
+}
+
+qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
+                                  const int64_t *v_offsets, const int64_t *pix_counts,
+                                  const int64_t *out_offsets, int32_t *n_out_dev,
+                                  double *nbar_out_dev, qa_stats *stats, void *hip_stream)
+{
+    g_err.clear();
+    (void)probs; (void)n_diag; (void)V_dev; (void)v_offsets; (void)pix_counts;
+    (void)out_offsets; (void)n_out_dev; (void)nbar_out_dev; (void)stats; (void)hip_stream;
+    return fail(QA_E_UNSUPPORTED, "batched entry point not built yet");
+}
+
+void qa_timing_enable(int on) { g_timing = on != 0; }
+
+void qa_timing_reset(void *hip_stream)
+{
+    Workspace *w;
+    if (get_ws((hipStream_t)hip_stream, &w) == QA_OK) w->ev_used = 0;
+}
+
+qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out)
+{
+    g_err.clear();
+    if (!ms_out) return fail(QA_E_NULL, "ms_out is NULL");
+    Workspace *w;
+    qa_status st;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    QA_HIP(hipStreamSynchronize(w->stream));
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < w->ev_used; ++i) {
+        for (int s = 0; s < 3; ++s) {
+            float ms = 0.0f;
+            QA_HIP(hipEventElapsedTime(&ms, w->ev[i][s], w->ev[i][s + 1]));
+            acc[s] += ms;
+        }
+    }
+    for (int s = 0; s < 3; ++s) ms_out[s] = acc[s];
+    if (calls_out) *calls_out = w->ev_used;
+    return QA_OK;
+}
+
+const char *qa_last_error(void) { return g_err.c_str(); }
+
+void qa_release(void *hip_stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_ws.find(std::make_pair(dev, (hipStream_t)hip_stream));
+        if (it == g_ws.end()) return;
+        w = it->second;
+        g_ws.erase(it);
+    }
+    (void)hipStreamSynchronize(w->stream);
+    (void)hipFree(w->dr);
+    (void)hipFree(w->pr);
+    (void)hipFree(w->qp_list);
+    (void)hipFree(w->flag_list);
+    (void)hipFree(w->counters);
+    (void)hipFree(w->acc);
+    for (auto &e : w->ev)
+        for (auto &x : e) (void)hipEventDestroy(x);
+    delete w;
+}
+
+const char *qa_version(void) { return "qarray-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// qa_internal.h -- device-side records and launch wrappers of libqarray.
+//
+// Layout in HBM (one call = one diagram unless batched):
+//   DiagRec  : per diagram, written by the prologue kernel (k_prep):
+//              C_dd, A = C_dd^{-1} (FP64, symmetric), C_gd, C_dd 1, sums,
+//              and the FP32 / split-BF16 tables the matrix-core scorer reads.
+//   PixRec   : per pixel, written by the setup kernels (k_setup / k_qp):
+//              the candidate description (n0, free mask, k) and the FP64
+//              gradient g0 = A (n0 - x_u) and energy U(n0) at the base state.
+//   SavedRec : per pixel, the softargmin state the adjoint needs (the
+//              caller-owned "saved" buffer of qa_soft_charge).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qa {
+
+constexpr int kMaxDot = 16;
+constexpr int kMaxGate = 32;
+constexpr int kWave = 64;
+
+// counters (int64) kept in the workspace, mirrored into qa_stats
+enum Counter {
+    C_PIXELS = 0,
+    C_QP = 1,
+    C_QP_FAIL = 2,
+    C_DOUBLED = 3,
+    C_NEAR_TIE = 4,
+    C_GAP_1E9 = 5,
+    C_CANDIDATES = 6,
+    C_QP_LIST = 7,      // length of the QP pixel list
+    C_FLAG_LIST = 8,    // length of the full FP64 re-score list
+    C_BAND_OVERFLOW = 9,
+    C_NUM = 16
+};
+
+struct alignas(16) DiagRec {
+    int32_t n, g, closed, nhat;
+    double kT, t;
+    int32_t prec, pad0;
+    double one_c;                 // 1^T C_dd 1
+    double c[kMaxDot];            // C_dd 1
+    double Cdd[kMaxDot * kMaxDot];
+    double A[kMaxDot * kMaxDot];  // C_dd^{-1}
+    double Cgd[kMaxDot * kMaxGate];
+    // matrix-core tables (dense box, n >= 9): low part = dots 0..7,
+    // high part = dots 8..n-1; see qa_mfma.hip
+    float T1[16][8];              // A_LH b_hi for the 4 row bits of the high index
+    float T2[16][8];              // A_LH b_hi for the next 4 bits of the high index
+    float Hhi[256];               // 1/2 b_hi^T A_HH b_hi
+    float hlo[256];               // 1/2 b_lo^T A_LL b_lo
+    float sumabs;                 // sum |A_ij| / 2, bound used by the error band
+    float pad1[3];
+};
+
+struct alignas(8) PixRec {
+    double g0[kMaxDot];   // A (n0 - x_u)
+    double u0;            // U(n0)
+    int16_t n0[kMaxDot];  // base state of the candidate set
+    uint32_t free;        // dots that take both roundings
+    int32_t k;            // closed: number of raised free dots; -1 open
+    int32_t flags;        // bit0 QP path, bit1 QP failure, bit2 threshold doubled
+    int32_t pad;
+};
+
+struct alignas(8) SavedRec {
+    double emin;          // smallest candidate energy
+    double logZ;          // log sum exp(-(E - emin)/kT)
+    int16_t n0[kMaxDot];
+    uint32_t free;
+    int32_t k;
+};
+
+// -------------------------------------------------------------------------
+// launch wrappers (qa_kernels.hip); all enqueue on `s` and return the HIP
+// error of the launch.
+// -------------------------------------------------------------------------
+hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s);
+hipError_t launch_prep(DiagRec *dr, int n_diag, hipStream_t s);
+hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
+                        int32_t *qp_list, int64_t *counters, int n_dot, bool closed,
+                        hipStream_t s);
+hipError_t launch_qp(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
+                     const int32_t *qp_list, int64_t *counters, int n_dot, bool closed,
+                     hipStream_t s);
+// T = 0 argmin in FP64 over the listed pixels (list == nullptr: all P)
+hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P,
+                             const int32_t *list, const int64_t *list_count,
+                             int32_t *n_out, int64_t *counters, int n_dot, hipStream_t s);
+// matrix-core scorer for the dense box at T = 0; flags near ties into flag_list
+hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
+                             int32_t *n_out, int32_t *flag_list, int64_t *counters,
+                             int n_dot, hipStream_t s);
+hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
+                           SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s);
+hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P,
+                           const double *gbar, const SavedRec *saved, double *accA,
+                           double *accG, double *accU, double *gradV, int n_dot,
+                           hipStream_t s);
+hipError_t launch_soft_bwd_final(const DiagRec *dr, const double *accA, const double *accG,
+                                 const double *accU, double *grad_cdd, double *grad_cgd,
+                                 hipStream_t s);
+
+}  // namespace qa

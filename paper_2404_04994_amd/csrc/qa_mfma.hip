@@ -1,0 +1,408 @@
+// qa_mfma.hip -- matrix-core scorer for the dense floor/ceil box (Sec. 3.2.1)
+// at T = 0 (Eq. argmin), 9 <= N <= 16 dots, open arrays.
+//
+// Every candidate of pixel p is n0 + b, b in {0,1}^N, and (Eq. free_energy)
+//     U(n0 + b) - U(n0) = b^T g + 1/2 b^T A b,       g = A (n0 - x_u).
+// The box is split into a low part (dots 0..7, index c_lo, 256 values) and a
+// high part (dots 8..N-1, index c_hi).  With A_LH the low/high block of A,
+//     E(c_hi, c_lo) = b_lo^T g'(c_hi) + h_lo(c_lo) + C(c_hi),
+//     g'(c_hi)     = g_lo + A_LH b_hi,
+//     C(c_hi)      = b_hi^T g_hi + 1/2 b_hi^T A_HH b_hi,
+// so the pixels x candidates contraction becomes one matrix-core tile per
+// 16 high x 16 low indices: rows carry g' and C (they depend on the pixel),
+// columns carry the 0/1 patterns of b_lo and h_lo (the same for every pixel,
+// kept in registers for the whole kernel).  Each 16x16 tile is a single
+// v_mfma_f32_16x16x32_bf16 whose K = 32 slots hold
+//     chunk 0..2 : three BF16 parts of g' (exact truncation split of the FP32
+//                  value; BF16X2 keeps two round-to-nearest parts) x b_lo bits
+//     chunk 3    : three parts of C x 1 and 1 x three parts of h_lo,
+// so the tile is the complete energy, accumulated in FP32.  The FP32 form
+// uses three v_mfma_f32_16x16x4_f32 per tile instead (K = 4 each: g'[0..3],
+// g'[4..7], and {C, 1} against {1, h_lo}).
+//
+// Epilogue: a running minimum (v_min3) per lane and high-index row tile;
+// the lane/row-tile minima give the best value and a certified runner-up
+// bound; the winning row tile is recomputed to recover the index and the
+// runner-up inside it.  When the runner-up lies within twice the certified
+// error bound of the best, the exact argmin is one of the states whose
+// approximate energy lies within that band of the best: the wave sweeps the
+// box once more, collects those states (at most 256) and scores them in FP64
+// (ties to the lexicographically smallest state); a larger band sends the
+// pixel to the full FP64 scorer.  Otherwise n* = n0 + b is written directly.
+#include "qa_internal.h"
+
+namespace qa {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+union Pack8 {
+    uint32_t u[4];
+    bf16x8_t v;
+};
+
+__device__ __forceinline__ uint32_t fbits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ float trunc16(float x)
+{
+    return __uint_as_float(__float_as_uint(x) & 0xFFFF0000u);
+}
+// round to nearest even at 16 significant bits (finite inputs)
+__device__ __forceinline__ float rne16(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return __uint_as_float((b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u);
+}
+// two FP32 values whose low 16 bits are zero -> packed BF16 pair
+__device__ __forceinline__ uint32_t pack2(float lo, float hi)
+{
+    return (fbits(lo) >> 16) | (fbits(hi) & 0xFFFF0000u);
+}
+
+constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
+constexpr int kMaxBand = 256;  // near-tie states re-scored in FP64 inside the kernel
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ dr,
+                                                    const PixRec *__restrict__ pr, int64_t P,
+                                                    int32_t *__restrict__ n_out,
+                                                    int32_t *__restrict__ flag_list,
+                                                    int64_t *__restrict__ counters)
+{
+    __shared__ float sT1[16][8];
+    __shared__ float sT2[16][8];
+    __shared__ float sH[256];
+    __shared__ double sA64[kMaxDot * kMaxDot];
+    __shared__ int sband[4][kMaxBand];
+    __shared__ int sbandn[4];
+    __shared__ double sG64[4][kMaxDot];
+    __shared__ unsigned long long sflag, sover, sgap;
+    for (int e = threadIdx.x; e < 128; e += blockDim.x) {
+        sT1[e / 8][e % 8] = dr->T1[e / 8][e % 8];
+        sT2[e / 8][e % 8] = dr->T2[e / 8][e % 8];
+    }
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        sH[e] = dr->Hhi[e];
+        sA64[e] = dr->A[e];
+    }
+    if (threadIdx.x == 0) { sflag = 0; sover = 0; sgap = 0; }
+    __syncthreads();
+
+    const int n = dr->n;
+    const int nh = n - 8;
+    const int nrt = nh > 4 ? 1 << (nh - 4) : 1;
+    const int lane = threadIdx.x & 63;
+    const int q = lane >> 4;     // K chunk of this lane's A/B operand slots
+    const int mrow = lane & 15;  // A row (high index within tile) = B column (low index)
+    const float sumabs = dr->sumabs;
+
+    // ---- pixel-independent column operands, one set per 16-wide low tile ----
+    uint32_t bw[16][4];
+    float bf[16][3];
+#pragma unroll
+    for (int ct = 0; ct < 16; ++ct) {
+        const int clo = ct * 16 + mrow;
+        const float h = dr->hlo[clo];
+        if (PREC == kPrecFP32) {
+            bf[ct][0] = (float)((clo >> q) & 1);
+            bf[ct][1] = (float)((clo >> (4 + q)) & 1);
+            bf[ct][2] = (q == 0) ? 1.0f : (q == 1 ? h : 0.0f);
+        } else {
+            if (q < 3) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    bw[ct][d] = ((clo >> (2 * d) & 1) ? 0x3F80u : 0u) |
+                                ((clo >> (2 * d + 1) & 1) ? 0x3F800000u : 0u);
+            } else {
+                const float h1 = trunc16(h);
+                const float r = h - h1;
+                const float h2 = trunc16(r);
+                const float h3 = r - h2;  // exact in BF16
+                bw[ct][0] = 0x3F803F80u;
+                bw[ct][1] = 0x3F80u | (fbits(h1) & 0xFFFF0000u);
+                bw[ct][2] = pack2(h2, h3);
+                bw[ct][3] = 0u;
+            }
+        }
+    }
+
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t nflag = 0, nover = 0, ngap = 0;
+    for (int64_t pw = wave; pw < P; pw += nwaves) {
+        const int64_t p = __builtin_amdgcn_readfirstlane((int)pw);
+        const PixRec *r = pr + p;
+        float g[16];
+        float gabs = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            g[i] = (i < n) ? (float)r->g0[i] : 0.0f;
+            gabs += fabsf(g[i]);
+        }
+        // per-lane row constants: G1 = g_lo + A_LH b_hi(row bits), P1 = b_hi(row)^T g_hi
+        float G1[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) G1[i] = g[i] + sT1[mrow][i];
+        float P1 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (mrow >> j & 1) P1 += g[8 + j];
+
+        // build the A operand of row tile rt for this lane
+        auto build_a = [&](int rt, Pack8 &a, float (&af)[3]) {
+            float P2 = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (rt >> j & 1) P2 += g[12 + j];
+            const float C = (P1 + P2) + sH[rt * 16 + mrow];
+            if (PREC == kPrecFP32) {
+                float v0 = 0.0f, v1 = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (q == j) {
+                        v0 = G1[j] + sT2[rt][j];
+                        v1 = G1[4 + j] + sT2[rt][4 + j];
+                    }
+                }
+                af[0] = v0;
+                af[1] = v1;
+                af[2] = (q == 0) ? C : (q == 1 ? 1.0f : 0.0f);
+            } else {
+                float v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = G1[j] + sT2[rt][j];
+                if (PREC == kPrecX3) {
+                    // exact three-way split: part q of v is the BF16 truncation
+                    // of v after removing q leading BF16 parts
+                    const uint32_t m1 = q >= 1 ? 0xFFFF0000u : 0u;
+                    const uint32_t m2 = q >= 2 ? 0xFFFF0000u : 0u;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        v[j] -= __uint_as_float(fbits(v[j]) & m1);
+                        v[j] -= __uint_as_float(fbits(v[j]) & m2);
+                        v[j] = trunc16(v[j]);
+                    }
+                } else {
+                    // two round-to-nearest parts; chunk 2 unused
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const float s1 = rne16(v[j]);
+                        const float s2 = rne16(v[j] - s1);
+                        v[j] = (q == 0) ? s1 : (q == 1 ? s2 : 0.0f);
+                    }
+                }
+                if (q == 3) {
+                    const float c1 = trunc16(C);
+                    const float cr = C - c1;
+                    const float c2 = trunc16(cr);
+                    const float c3 = cr - c2;  // exact in BF16
+                    v[0] = c1; v[1] = c2; v[2] = c3;
+                    v[3] = 1.0f; v[4] = 1.0f; v[5] = 1.0f;
+                    v[6] = 0.0f; v[7] = 0.0f;
+                }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) a.u[d] = pack2(v[2 * d], v[2 * d + 1]);
+            }
+        };
+        auto tile = [&](const Pack8 &a, const float (&af)[3], int ct) -> f32x4_t {
+            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (PREC == kPrecFP32) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[ct][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[ct][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[ct][2], acc, 0, 0, 0);
+            } else {
+                Pack8 b;
+                b.u[0] = bw[ct][0]; b.u[1] = bw[ct][1]; b.u[2] = bw[ct][2]; b.u[3] = bw[ct][3];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+            }
+            return acc;
+        };
+
+        // ---- main sweep: minimum per (lane, row tile) ----
+        float best1 = INFINITY, best2 = INFINITY;
+        int rt1 = 0;
+        for (int rt = 0; rt < nrt; ++rt) {
+            Pack8 a;
+            float af[3];
+            build_a(rt, a, af);
+            float gm = INFINITY;
+#pragma unroll
+            for (int ct = 0; ct < 16; ++ct) {
+                const f32x4_t d = tile(a, af, ct);
+                gm = fminf(fminf(gm, d[0]), d[1]);
+                gm = fminf(fminf(gm, d[2]), d[3]);
+            }
+            if (gm < best1) { best2 = best1; best1 = gm; rt1 = rt; }
+            else best2 = fminf(best2, gm);
+        }
+        // ---- best group over the wave and the runner-up among group minima ----
+        float wmin = best1;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) wmin = fminf(wmin, __shfl_xor(wmin, off));
+        const unsigned long long hit = __ballot(best1 == wmin);
+        const int winner = __ffsll((long long)hit) - 1;
+        float other = (lane == winner) ? best2 : best1;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) other = fminf(other, __shfl_xor(other, off));
+        const int rtw = __shfl(rt1, winner);
+        // ---- recompute the winning row tile: index and in-group runner-up ----
+        float v1 = INFINITY, v2 = INFINITY;
+        int i1 = 0;
+        {
+            Pack8 a;
+            float af[3];
+            build_a(rtw, a, af);
+#pragma unroll
+            for (int ct = 0; ct < 16; ++ct) {
+                const f32x4_t d = tile(a, af, ct);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float e = d[i];
+                    if (e < v1) { v2 = v1; v1 = e; i1 = ct * 4 + i; }
+                    else v2 = fminf(v2, e);
+                }
+            }
+        }
+        const float e1 = __shfl(v1, winner);
+        const int iw = __shfl(i1, winner);
+        const float e2 = fminf(other, __shfl(v2, winner));
+        // Certified bound on |E_approx - E| for every candidate of the pixel.
+        // All inputs of the tile sum are bounded by S = sum|g| + 1/2 sum|A|
+        // (g' parts, C parts and h parts together), FP32 rounding of the
+        // operands adds a few 2^-24 S and the 32-term FP32 accumulation at most
+        // 31 * 2^-24 S (2^-23 per term if the hardware truncates); 2^-17 S
+        // covers that with room to spare.  Two-part BF16 adds the 2^-16 |g'|
+        // truncation of the split.
+        const float S = gabs + sumabs;
+        const float delta = (PREC == kPrecX2 ? 0x1p-15f : 0x1p-17f) * S;
+        const bool tie = !(e2 - e1 > 2.0f * delta);
+        if (!tie) {
+            if (lane < n) {
+                const int ct = iw >> 2, i = iw & 3;
+                const int row = 4 * (winner >> 4) + i;
+                const uint32_t chi = (uint32_t)(rtw * 16 + row);
+                const uint32_t clo = (uint32_t)(ct * 16 + (winner & 15));
+                const uint32_t b = clo | (chi << 8);
+                n_out[p * n + lane] = (int32_t)r->n0[lane] + (int32_t)((b >> lane) & 1u);
+            }
+            continue;
+        }
+        // ---- near tie: every candidate within 2 delta of the best holds the
+        // exact argmin; collect them and score them in FP64 ----
+        ++nflag;
+        const float thr = e1 + 2.0f * delta;
+        int *band = sband[threadIdx.x >> 6];
+        int *bandn = &sbandn[threadIdx.x >> 6];
+        if (lane == 0) *bandn = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int rt = 0; rt < nrt; ++rt) {
+            Pack8 a;
+            float af[3];
+            build_a(rt, a, af);
+#pragma unroll
+            for (int ct = 0; ct < 16; ++ct) {
+                const f32x4_t d = tile(a, af, ct);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (d[i] <= thr) {
+                        const int slot = atomicAdd(bandn, 1);
+                        if (slot < kMaxBand) {
+                            const uint32_t chi = (uint32_t)(rt * 16 + 4 * q + i);
+                            band[slot] = (int)((uint32_t)(ct * 16 + mrow) | (chi << 8));
+                        }
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int cnt = *bandn;
+        if (cnt > kMaxBand) {
+            // too many states in the band: the full FP64 pass decides
+            if (lane == 0) {
+                const unsigned long long slot =
+                    atomicAdd((unsigned long long *)&counters[C_FLAG_LIST], 1ull);
+                flag_list[slot] = (int32_t)p;
+                ++nover;
+            }
+            continue;
+        }
+        double *g64 = sG64[threadIdx.x >> 6];
+        if (lane < kMaxDot) g64[lane] = (lane < n) ? r->g0[lane] : 0.0;
+        __builtin_amdgcn_wave_barrier();
+        double b1 = INFINITY, b2 = INFINITY;
+        uint32_t c1 = 0;
+        for (int j = lane; j < cnt; j += 64) {
+            const uint32_t c = (uint32_t)band[j];
+            // U(n0 + b) - U(n0) = sum_i b_i (g_i + 1/2 sum_k b_k A_ik)
+            double e = 0.0;
+#pragma unroll 1
+            for (int i = 0; i < n; ++i) {
+                if (c >> i & 1u) {
+                    double s = g64[i];
+#pragma unroll 4
+                    for (int k = 0; k < kMaxDot; ++k)
+                        if (c >> k & 1u) s += 0.5 * sA64[i * kMaxDot + k];
+                    e += s;
+                }
+            }
+            if (e < b1 || (e == b1 && __brev(c) < __brev(c1))) { b2 = b1; b1 = e; c1 = c; }
+            else b2 = fmin(b2, e);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ob1 = __shfl_xor(b1, off);
+            const double ob2 = __shfl_xor(b2, off);
+            const uint32_t oc1 = __shfl_xor(c1, off);
+            if (ob1 < b1 || (ob1 == b1 && __brev(oc1) < __brev(c1))) {
+                b2 = fmin(b1, ob2); b1 = ob1; c1 = oc1;
+            } else {
+                b2 = fmin(b2, ob1);
+            }
+        }
+        if (lane < n) n_out[p * n + lane] = (int32_t)r->n0[lane] + (int32_t)((c1 >> lane) & 1u);
+        if (lane == 0 && b2 - b1 < 1e-9) ++ngap;
+    }
+    if (lane == 0) {
+        if (nflag) atomicAdd(&sflag, (unsigned long long)nflag);
+        if (nover) atomicAdd(&sover, (unsigned long long)nover);
+        if (ngap) atomicAdd(&sgap, (unsigned long long)ngap);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (sflag) atomicAdd((unsigned long long *)&counters[C_NEAR_TIE], sflag);
+        if (sover) atomicAdd((unsigned long long *)&counters[C_BAND_OVERFLOW], sover);
+        if (sgap) atomicAdd((unsigned long long *)&counters[C_GAP_1E9], sgap);
+        // every pixel scores all 2^n candidates of its box on the matrix cores
+        if (blockIdx.x == 0)
+            atomicAdd((unsigned long long *)&counters[C_CANDIDATES],
+                      (unsigned long long)P << n);
+    }
+}
+
+hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
+                             int32_t *n_out, int32_t *flag_list, int64_t *counters, int n_dot,
+                             hipStream_t s)
+{
+    if (n_dot < 9 || n_dot > 16) return hipErrorInvalidValue;
+    int64_t blocks = (P + 3) / 4;  // one wave per pixel, four waves per block
+    if (blocks > 65536) blocks = 65536;
+    const dim3 grid((unsigned)blocks), block(256);
+    switch (prec) {
+    case kPrecFP32:
+        hipLaunchKernelGGL(k_score_mfma<kPrecFP32>, grid, block, 0, s, dr, pr, P, n_out,
+                           flag_list, counters);
+        break;
+    case kPrecX3:
+        hipLaunchKernelGGL(k_score_mfma<kPrecX3>, grid, block, 0, s, dr, pr, P, n_out, flag_list,
+                           counters);
+        break;
+    case kPrecX2:
+        hipLaunchKernelGGL(k_score_mfma<kPrecX2>, grid, block, 0, s, dr, pr, P, n_out, flag_list,
+                           counters);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qa

@@ -1,0 +1,229 @@
+"""Thin Python binding of libqarray.so (C ABI in include/qarray.h).
+
+Argument marshalling only: every step of the ground-state path runs in the
+HIP kernels of the library.  torch supplies device memory and streams.  The
+binding fails loudly (``QArrayError``) when the library or a GPU is missing;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqarray.so")
+
+QA_OPEN, QA_CLOSED = 0, 1
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
+STATUS = {0: "QA_OK", 1: "QA_E_NULL", 2: "QA_E_SHAPE", 3: "QA_E_NOT_SYMMETRIC", 4: "QA_E_NOT_PD",
+          5: "QA_E_RANGE", 6: "QA_E_UNSUPPORTED", 7: "QA_E_WORKSPACE", 8: "QA_E_DEVICE"}
+EXPORTS = ("qa_ground_state", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
+           "qa_ground_state_batched", "qa_last_error", "qa_release", "qa_version",
+           "qa_timing_enable", "qa_timing_reset", "qa_timing_sum")
+
+
+class QArrayError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_dot", C.c_int32), ("n_gate", C.c_int32),
+                ("cdd", C.POINTER(C.c_double)), ("cgd", C.POINTER(C.c_double)),
+                ("mode", C.c_int32), ("n_charge", C.c_int32),
+                ("kT", C.c_double), ("threshold", C.c_double),
+                ("precision", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(name, C.c_int64) for name in
+                ("pixels", "qp_pixels", "qp_failures", "doubled_pixels", "near_tie_pixels",
+                 "fp64_gap_below_1e9", "candidates", "band_overflow")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libqarray.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise QArrayError(6, "libqarray.so not built (run paper_2404_04994_amd.build)")
+        lib = C.CDLL(LIB_PATH)
+        vp, pb, st = C.c_void_p, C.POINTER(Problem), C.POINTER(Stats)
+        i64p = C.POINTER(C.c_int64)
+        lib.qa_ground_state.argtypes = [pb, vp, C.c_int64, vp, st, vp]
+        lib.qa_soft_charge.argtypes = [pb, vp, C.c_int64, vp, vp, st, vp]
+        lib.qa_soft_charge_backward.argtypes = [pb, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
+        lib.qa_ground_state_batched.argtypes = [pb, C.c_int32, vp, i64p, i64p, i64p, vp, vp, st, vp]
+        lib.qa_saved_bytes.argtypes = [C.c_int64, C.c_int32]
+        lib.qa_saved_bytes.restype = C.c_size_t
+        lib.qa_last_error.restype = C.c_char_p
+        lib.qa_version.restype = C.c_char_p
+        lib.qa_release.argtypes = [vp]
+        lib.qa_timing_enable.argtypes = [C.c_int]
+        lib.qa_timing_reset.argtypes = [vp]
+        lib.qa_timing_sum.argtypes = [vp, C.POINTER(C.c_double), i64p]
+        lib.qa_timing_sum.restype = C.c_int
+        for f in ("qa_ground_state", "qa_soft_charge", "qa_soft_charge_backward",
+                  "qa_ground_state_batched"):
+            getattr(lib, f).restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise QArrayError(status, load().qa_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _host(m):
+    if isinstance(m, torch.Tensor):
+        m = m.detach().cpu().numpy()
+    return np.ascontiguousarray(m, dtype=np.float64)
+
+
+def make_problem(cdd, cgd, closed=False, nhat=0, kT=0.0, t=1.0, precision="fp64"):
+    """Problem struct plus the host arrays it points into (keep both alive)."""
+    cdd, cgd = _host(cdd), _host(cgd)
+    if cdd.ndim != 2 or cgd.ndim != 2 or cdd.shape[0] != cdd.shape[1] or cgd.shape[0] != cdd.shape[0]:
+        raise QArrayError(2, "cdd must be N x N and cgd N x G")
+    prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    pb = Problem(cdd.shape[0], cgd.shape[1], cdd.ctypes.data_as(C.POINTER(C.c_double)),
+                 cgd.ctypes.data_as(C.POINTER(C.c_double)), QA_CLOSED if closed else QA_OPEN,
+                 int(nhat), float(kT), float(t), prec, 0)
+    return pb, (cdd, cgd)
+
+
+def _device_V(V, n_gate):
+    if not isinstance(V, torch.Tensor):
+        V = torch.as_tensor(np.asarray(V, np.float64))
+    if not V.is_cuda:
+        V = V.cuda()
+    V = V.to(torch.float64).contiguous().view(-1, n_gate)
+    return V
+
+
+def ground_state(cdd, cgd, V, closed=False, nhat=0, t=1.0, precision="fp64", stream=None,
+                 stats=False, out=None):
+    """T = 0 ground state of every pixel (Eq. argmin); int32 tensor (P, N) on the GPU.
+    With stats=True returns (n, stats_dict) and waits for the stream."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, 0.0, t, precision)
+    V = _device_V(V, pb.n_gate)
+    P = V.shape[0]
+    if out is None:
+        out = torch.empty((P, pb.n_dot), dtype=torch.int32, device=V.device)
+    st = Stats() if stats else None
+    _check(lib.qa_ground_state(C.byref(pb), C.c_void_p(V.data_ptr()), P,
+                               C.c_void_p(out.data_ptr()), C.byref(st) if st else None,
+                               _stream(stream)))
+    del keep
+    return (out, st.as_dict()) if stats else out
+
+
+def saved_bytes(P: int, n_dot: int) -> int:
+    return int(load().qa_saved_bytes(P, n_dot))
+
+
+def soft_charge(cdd, cgd, V, kT, closed=False, nhat=0, t=1.0, stream=None, stats=False):
+    """Softargmin (Sec. 4.2) per pixel: (nbar float64 (P, N), saved uint8 buffer[, stats])."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, kT, t, "fp64")
+    V = _device_V(V, pb.n_gate)
+    P = V.shape[0]
+    nbar = torch.empty((P, pb.n_dot), dtype=torch.float64, device=V.device)
+    saved = torch.empty(max(saved_bytes(P, pb.n_dot), 1), dtype=torch.uint8, device=V.device)
+    st = Stats() if stats else None
+    _check(lib.qa_soft_charge(C.byref(pb), C.c_void_p(V.data_ptr()), P,
+                              C.c_void_p(nbar.data_ptr()), C.c_void_p(saved.data_ptr()),
+                              C.byref(st) if st else None, _stream(stream)))
+    del keep
+    return (nbar, saved, st.as_dict()) if stats else (nbar, saved)
+
+
+def soft_charge_backward(cdd, cgd, V, kT, grad_nbar, saved, closed=False, nhat=0, t=1.0,
+                         want_V=True, stream=None):
+    """Adjoint of soft_charge: (dL/dC_dd, dL/dC_gd, dL/dV or None), FP64 device tensors."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, kT, t, "fp64")
+    V = _device_V(V, pb.n_gate)
+    P = V.shape[0]
+    g = grad_nbar.to(torch.float64).contiguous()
+    dC = torch.empty((pb.n_dot, pb.n_dot), dtype=torch.float64, device=V.device)
+    dG = torch.empty((pb.n_dot, pb.n_gate), dtype=torch.float64, device=V.device)
+    dV = torch.empty_like(V) if want_V else None
+    _check(lib.qa_soft_charge_backward(C.byref(pb), C.c_void_p(V.data_ptr()), P,
+                                       C.c_void_p(g.data_ptr()), C.c_void_p(saved.data_ptr()),
+                                       C.c_void_p(dC.data_ptr()), C.c_void_p(dG.data_ptr()),
+                                       C.c_void_p(dV.data_ptr()) if dV is not None else None,
+                                       _stream(stream)))
+    del keep
+    return dC, dG, dV
+
+
+class SoftCharge(torch.autograd.Function):
+    """<n> = softargmin over the candidate set, differentiable in C_dd, C_gd and V.
+    The backward recomputes candidate energies on the GPU (nothing but the
+    per-pixel candidate set and normaliser is saved)."""
+
+    @staticmethod
+    def forward(ctx, cdd, cgd, V, kT, closed=False, nhat=0, t=1.0):
+        nbar, saved = soft_charge(cdd, cgd, V, kT, closed, nhat, t)
+        ctx.save_for_backward(cdd, cgd, V)
+        ctx.saved_buf = saved
+        ctx.args = (float(kT), bool(closed), int(nhat), float(t))
+        return nbar
+
+    @staticmethod
+    def backward(ctx, grad_nbar):
+        cdd, cgd, V = ctx.saved_tensors
+        kT, closed, nhat, t = ctx.args
+        dC, dG, dV = soft_charge_backward(cdd, cgd, V, kT, grad_nbar, ctx.saved_buf, closed, nhat,
+                                          t, want_V=ctx.needs_input_grad[2])
+        dC = dC.to(cdd.device, cdd.dtype) if ctx.needs_input_grad[0] else None
+        dG = dG.to(cgd.device, cgd.dtype) if ctx.needs_input_grad[1] else None
+        dV = dV.to(V.device, V.dtype).view_as(V) if ctx.needs_input_grad[2] else None
+        return dC, dG, dV, None, None, None, None
+
+
+def soft_charge_autograd(cdd, cgd, V, kT, closed=False, nhat=0, t=1.0):
+    return SoftCharge.apply(cdd, cgd, V, kT, closed, nhat, t)
+
+
+def timing_enable(on: bool = True):
+    load().qa_timing_enable(1 if on else 0)
+
+
+def timing_reset(stream=None):
+    load().qa_timing_reset(_stream(stream))
+
+
+def timing_sum(stream=None):
+    """(ms per stage [setup, scoring, re-score] summed since the reset, calls)."""
+    ms = (C.c_double * 3)()
+    calls = C.c_int64(0)
+    _check(load().qa_timing_sum(_stream(stream), ms, C.byref(calls)))
+    return [ms[0], ms[1], ms[2]], int(calls.value)
+
+
+def release(stream=None):
+    load().qa_release(_stream(stream))
+
+
+def version() -> str:
+    return load().qa_version().decode()

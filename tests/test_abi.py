@@ -1,0 +1,105 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and host validation rejects bad input before any device
+work (these calls return before touching a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qarray.h")
+
+
+@pytest.fixture(scope="module")
+def qa():
+    from paper_2404_04994_amd import qarray
+    try:
+        qarray.load()
+    except Exception as e:  # pragma: no cover - build() runs before the suite
+        pytest.fail("libqarray.so missing: %s" % e)
+    return qarray
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:qa_status|size_t|const char \*|void)\s*\n?\s*\*?(qa_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("qa_ground_state", "qa_soft_charge", "qa_soft_charge_backward",
+              "qa_ground_state_batched", "qa_saved_bytes", "qa_last_error", "qa_release",
+              "qa_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(qa):
+    lib = qa.load()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(qa.EXPORTS) <= set(declared_functions())
+    assert "gfx950" in qa.version()
+
+
+def _call_gs(qa, cdd, cgd, P=4, **kw):
+    pb, keep = qa.make_problem(cdd, cgd, **kw)
+    out = qa.load().qa_ground_state(C.byref(pb), C.c_void_p(16), P, C.c_void_p(16), None, None)
+    return out, qa.load().qa_last_error().decode()
+
+
+GOOD_CDD = np.array([[1.2, -0.2], [-0.2, 1.1]])
+GOOD_CGD = np.array([[0.8, 0.1], [0.1, 0.9]])
+
+
+@pytest.mark.parametrize("cdd,cgd,kw,status", [
+    (np.array([[1.2, -0.2], [-0.25, 1.1]]), GOOD_CGD, {}, 3),          # not symmetric
+    (np.array([[1.0, -2.0], [-2.0, 1.0]]), GOOD_CGD, {}, 4),           # not PD
+    (np.array([[np.nan, 0.0], [0.0, 1.0]]), GOOD_CGD, {}, 5),          # not finite
+    (GOOD_CDD, GOOD_CGD, dict(t=1.5), 5),                              # t > 1
+    (GOOD_CDD, GOOD_CGD, dict(t=-0.1), 5),                             # t < 0
+    (GOOD_CDD, GOOD_CGD, dict(closed=True, nhat=-1), 5),               # N_hat < 0
+    (GOOD_CDD, GOOD_CGD, dict(precision=7), 5),                        # bad enum
+])
+def test_validation_errors(qa, cdd, cgd, kw, status):
+    st, msg = _call_gs(qa, cdd, cgd, **kw)
+    assert st == status and msg
+
+
+def test_shape_errors(qa):
+    lib = qa.load()
+    big = np.eye(17)
+    pb, keep = qa.make_problem(big, np.eye(17))
+    assert lib.qa_ground_state(C.byref(pb), C.c_void_p(16), 4, C.c_void_p(16), None, None) == 2
+    pb, keep = qa.make_problem(GOOD_CDD, np.ones((2, 33)))
+    assert lib.qa_ground_state(C.byref(pb), C.c_void_p(16), 4, C.c_void_p(16), None, None) == 2
+    pb, keep = qa.make_problem(GOOD_CDD, GOOD_CGD)
+    assert lib.qa_ground_state(C.byref(pb), C.c_void_p(16), -1, C.c_void_p(16), None, None) == 2
+    assert lib.qa_ground_state(None, C.c_void_p(16), 4, C.c_void_p(16), None, None) == 1
+    assert lib.qa_ground_state(C.byref(pb), None, 4, C.c_void_p(16), None, None) == 1
+
+
+def test_soft_needs_positive_temperature(qa):
+    lib = qa.load()
+    pb, keep = qa.make_problem(GOOD_CDD, GOOD_CGD, kT=0.0)
+    st = lib.qa_soft_charge(C.byref(pb), C.c_void_p(16), 4, C.c_void_p(16), None, None, None)
+    assert st == 5
+    pb, keep = qa.make_problem(np.eye(13), np.eye(13), kT=0.1)
+    st = lib.qa_soft_charge_backward(C.byref(pb), C.c_void_p(16), 4, C.c_void_p(16),
+                                     C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None, None)
+    assert st == 6
+
+
+def test_empty_input_is_a_noop(qa):
+    lib = qa.load()
+    pb, keep = qa.make_problem(GOOD_CDD, GOOD_CGD)
+    st = qa.Stats()
+    assert lib.qa_ground_state(C.byref(pb), None, 0, None, C.byref(st), None) == 0
+    assert st.pixels == 0
+
+
+def test_saved_bytes(qa):
+    assert qa.saved_bytes(0, 4) == 0
+    assert qa.saved_bytes(10, 4) == 10 * qa.saved_bytes(1, 4) > 0
