@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--batch-diagrams", type=int, default=4096)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -247,6 +248,27 @@ def run_extras(qa, W, torch, d, V, out, args):
                        "near_tie_pixels": st["near_tie_pixels"]}
         log("form %s: %s" % (prec, forms[prec]))
     res["forms_16dot"] = forms
+    # thresholded candidate sets of the same diagram (Sec. 3.2.2), FP64 scoring
+    pruned = {}
+    for t in (2 / 3, 1 / 2, 1 / 3):
+        dt = W.grid4x4(200, t=t)
+        call = direct_gs(qa, dt, V, out, "fp64", torch)
+        wall = timed_calls(call, max(5, steps // 4), 2, torch)
+        _, st = qa.ground_state(dt.cdd, dt.cgd, V, t=t, stats=True)
+        entry = {"pixels_per_s": round(dt.P * max(5, steps // 4) / wall, 1),
+                 "mean_candidates": round(st["candidates"] / dt.P, 1)}
+        try:
+            import oracle as O
+            idx = np.random.default_rng(3).choice(dt.P, 200, replace=False)
+            nt = out.cpu().numpy()[idx]
+            ex = O.exact_se(dt.cdd, dt.cgd, dt.V[idx])
+            tie = ex["e2"] - ex["e1"] < 1e-9
+            entry["differs_from_exact_sampled"] = "%d/200" % int(((nt != ex["n"]).any(1) & ~tie).sum())
+        except Exception as e:
+            entry["oracle_error"] = repr(e)
+        pruned["t=%.3f" % t] = entry
+        log("pruned t=%.3f: %s" % (t, entry))
+    res["thresholded_16dot"] = pruned
     # the small workloads
     small = {}
     for name, dg, kT in (("double dot (N=2), T=0", W.double_dot(0), 0.0),
@@ -282,6 +304,23 @@ def run_extras(qa, W, torch, d, V, out, args):
                                   "fwd_bwd_ms_per_diagram": round(1e3 * wb / steps, 4),
                                   "pixels": int(Va.shape[0])}
     log("adjoint: %s" % res["adjoint_8dot_sensor"])
+    # ragged dataset batch: 4096 diagrams of 2..8 dots, 64 x 64 pixels each
+    if args.batch_diagrams > 0:
+        t0 = time.perf_counter()
+        b = qa.Batch(W.ragged_batch(args.batch_diagrams, npix=64))
+        log("batch of %d diagrams packed in %.1f s" % (args.batch_diagrams, time.perf_counter() - t0))
+        b.run()  # first call: autotune + graph capture
+        torch.cuda.synchronize()
+        nb = max(3, steps // 10)
+        wall = timed_calls(lambda: b.run(), nb, 1, torch)
+        st = b.run(stats=True)
+        res["ragged_batch"] = {"diagrams": args.batch_diagrams, "pixels": b.pixels,
+                               "ms_per_batch": round(1e3 * wall / nb, 3),
+                               "pixels_per_s": round(b.pixels * nb / wall, 1),
+                               "diagrams_per_s": round(args.batch_diagrams * nb / wall, 1),
+                               "candidates": st["candidates"], "qp_pixels": st["qp_pixels"]}
+        log("ragged batch: %s" % res["ragged_batch"])
+        del b
     return res
 
 

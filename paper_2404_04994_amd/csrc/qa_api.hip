@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <array>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <string>
@@ -58,7 +60,33 @@ struct Workspace {
     // stage timing: event sets {start, after setup, after scoring, after re-score}
     std::vector<std::array<hipEvent_t, 4>> ev;
     int64_t ev_used = 0;
+    // ragged batch
+    BatchHdr *bhdr = nullptr;
+    int64_t bhdr_cap = 0;
+    double *bmats = nullptr;
+    int64_t bmats_cap = 0;
+    DiagRec *brecs = nullptr;
+    int64_t brecs_cap = 0;
+    hipStream_t cap_stream = nullptr;   // private stream used for graph capture
+    hipGraphExec_t graph = nullptr;
+    std::vector<int64_t> graph_key;
 };
+
+// autotuned launch shape of the batched kernel, per batch signature
+struct BatchTune {
+    int blocks;
+    bool by_size;  // work order: diagrams with more candidates first
+};
+std::map<std::vector<int64_t>, BatchTune> g_tune;
+bool g_autotune_env_read = false, g_autotune = true, g_graphs = true;
+
+void read_env()
+{
+    if (g_autotune_env_read) return;
+    g_autotune_env_read = true;
+    if (const char *e = getenv("QA_AUTOTUNE")) g_autotune = atoi(e) != 0;
+    if (const char *e = getenv("QA_GRAPHS")) g_graphs = atoi(e) != 0;
+}
 
 constexpr int64_t kMaxTimedCalls = 4096;
 bool g_timing = false;
@@ -322,15 +350,198 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
     return QA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// host-side description of a batch in a given work order
+struct BatchPlan {
+    std::vector<BatchHdr> hdr;
+    std::vector<double> mats;
+    int64_t tiles = 0;
+    int max_dot = 0;
+};
+
+void plan_batch(const qa_problem *probs, int32_t n_diag, const int64_t *v_offsets,
+                const int64_t *pix_counts, const int64_t *out_offsets, bool by_size,
+                BatchPlan &plan)
+{
+    std::vector<int> order(n_diag);
+    for (int d = 0; d < n_diag; ++d) order[d] = d;
+    if (by_size) {
+        // largest candidate sets first, so the tail of the queue is cheap
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return probs[a].n_dot > probs[b].n_dot;
+        });
+    }
+    plan.hdr.resize(n_diag);
+    plan.mats.clear();
+    plan.tiles = 0;
+    plan.max_dot = 0;
+    for (int j = 0; j < n_diag; ++j) {
+        const int d = order[j];
+        const qa_problem &pb = probs[d];
+        BatchHdr &h = plan.hdr[j];
+        h.n = pb.n_dot;
+        h.g = pb.n_gate;
+        h.closed = pb.mode == QA_CLOSED;
+        h.nhat = pb.mode == QA_CLOSED ? pb.n_charge : 0;
+        h.kT = pb.kT;
+        h.t = pb.threshold;
+        h.v_off = v_offsets[d];
+        h.out_off = out_offsets[d];
+        h.P = pix_counts[d];
+        h.mat_off = (int64_t)plan.mats.size();
+        h.tile0 = plan.tiles;
+        plan.mats.insert(plan.mats.end(), pb.cdd, pb.cdd + pb.n_dot * pb.n_dot);
+        plan.mats.insert(plan.mats.end(), pb.cgd, pb.cgd + pb.n_dot * pb.n_gate);
+        plan.tiles += (h.P + 63) / 64;
+        plan.max_dot = std::max(plan.max_dot, pb.n_dot);
+    }
+}
+
+qa_status upload_plan(Workspace *w, const BatchPlan &plan, int32_t n_diag)
+{
+    qa_status st;
+    if ((st = grow(w, w->bhdr, w->bhdr_cap, n_diag))) return st;
+    if ((st = grow(w, w->bmats, w->bmats_cap, (int64_t)plan.mats.size()))) return st;
+    if ((st = grow(w, w->brecs, w->brecs_cap, n_diag))) return st;
+    QA_HIP(hipMemcpyAsync(w->bhdr, plan.hdr.data(), sizeof(BatchHdr) * n_diag,
+                          hipMemcpyHostToDevice, w->stream));
+    QA_HIP(hipMemcpyAsync(w->bmats, plan.mats.data(), sizeof(double) * plan.mats.size(),
+                          hipMemcpyHostToDevice, w->stream));
+    return QA_OK;
+}
+
+// the device work of one batch: zero the counters and the queue, prologue of
+// every diagram, the persistent kernel
+qa_status enqueue_batch(Workspace *w, hipStream_t s, int32_t n_diag, const BatchPlan &plan,
+                        const double *V, int32_t *n_out, double *nbar, int blocks)
+{
+    QA_HIP(launch_zero_i64(w->counters, C_NUM, s));
+    QA_HIP(launch_prep_batch(w->bhdr, w->bmats, w->brecs, n_diag, s));
+    QA_HIP(launch_batch(w->bhdr, w->brecs, n_diag, plan.tiles, V, n_out, nbar, w->counters,
+                        plan.max_dot, blocks, s));
+    return QA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
                                   const int64_t *v_offsets, const int64_t *pix_counts,
                                   const int64_t *out_offsets, int32_t *n_out_dev,
                                   double *nbar_out_dev, qa_stats *stats, void *hip_stream)
 {
     g_err.clear();
-    (void)probs; (void)n_diag; (void)V_dev; (void)v_offsets; (void)pix_counts;
-    (void)out_offsets; (void)n_out_dev; (void)nbar_out_dev; (void)stats; (void)hip_stream;
-    return fail(QA_E_UNSUPPORTED, "batched entry point not built yet");
+    read_env();
+    if (n_diag < 0) return fail(QA_E_SHAPE, "n_diag=%d is negative", n_diag);
+    if (n_diag == 0) {
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return QA_OK;
+    }
+    if (!probs || !v_offsets || !pix_counts || !out_offsets)
+        return fail(QA_E_NULL, "probs or an offset array is NULL");
+    int64_t total = 0;
+    for (int d = 0; d < n_diag; ++d) {
+        qa_status st = validate(&probs[d], false);
+        if (st) return fail(st, "diagram %d: %s", d, g_err.c_str());
+        if (pix_counts[d] < 0 || v_offsets[d] < 0 || out_offsets[d] < 0)
+            return fail(QA_E_SHAPE, "diagram %d: negative pixel count or offset", d);
+        total += pix_counts[d];
+    }
+    if (total == 0) {
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return QA_OK;
+    }
+    if (!V_dev || !n_out_dev) return fail(QA_E_NULL, "V_dev or n_out_dev is NULL");
+    Workspace *w;
+    qa_status st;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+
+    // signature of the batch for the tuning cache
+    int max_dot = 0, n_soft = 0;
+    for (int d = 0; d < n_diag; ++d) {
+        max_dot = std::max(max_dot, probs[d].n_dot);
+        n_soft += probs[d].kT > 0.0;
+    }
+    std::vector<int64_t> sig = {n_diag, total, max_dot, n_soft > 0 && nbar_out_dev != nullptr};
+    BatchPlan plan;
+    auto it = g_tune.find(sig);
+    if (it == g_tune.end() && g_autotune) {
+        // time every candidate launch shape once on this very batch (each run
+        // writes the same outputs) and keep the fastest
+        int dev = 0, cus = 256;
+        QA_HIP(hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        hipEvent_t e0, e1;
+        QA_HIP(hipEventCreate(&e0));
+        QA_HIP(hipEventCreate(&e1));
+        BatchTune best{cus * 4, true};
+        float best_ms = 1e30f;
+        for (int by_size = 0; by_size < 2; ++by_size) {
+            plan_batch(probs, n_diag, v_offsets, pix_counts, out_offsets, by_size != 0, plan);
+            if ((st = upload_plan(w, plan, n_diag))) return st;
+            for (int mult : {2, 4, 8, 16}) {
+                const int blocks = cus * mult;
+                QA_HIP(hipEventRecord(e0, w->stream));
+                if ((st = enqueue_batch(w, w->stream, n_diag, plan, V_dev, n_out_dev, nbar_out_dev,
+                                        blocks)))
+                    return st;
+                QA_HIP(hipEventRecord(e1, w->stream));
+                QA_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                QA_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) { best_ms = ms; best = BatchTune{blocks, by_size != 0}; }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        it = g_tune.emplace(sig, best).first;
+    }
+    const BatchTune tune = (it != g_tune.end()) ? it->second : BatchTune{1024, true};
+    plan_batch(probs, n_diag, v_offsets, pix_counts, out_offsets, tune.by_size, plan);
+    if ((st = upload_plan(w, plan, n_diag))) return st;
+
+    if (!g_graphs) {
+        if ((st = enqueue_batch(w, w->stream, n_diag, plan, V_dev, n_out_dev, nbar_out_dev,
+                                tune.blocks)))
+            return st;
+        return read_stats(w, stats);
+    }
+    // one graph per (batch layout, buffers): zero kernel, prologue, persistent
+    // kernel; captured on a private stream, launched on the caller's
+    std::vector<int64_t> key = {n_diag, plan.tiles, plan.max_dot, tune.blocks,
+                                (int64_t)(uintptr_t)V_dev, (int64_t)(uintptr_t)n_out_dev,
+                                (int64_t)(uintptr_t)nbar_out_dev, (int64_t)(uintptr_t)w->bhdr,
+                                (int64_t)(uintptr_t)w->bmats, (int64_t)(uintptr_t)w->brecs};
+    if (!w->graph || w->graph_key != key) {
+        if (w->graph) {
+            QA_HIP(hipStreamSynchronize(w->stream));
+            (void)hipGraphExecDestroy(w->graph);
+            w->graph = nullptr;
+        }
+        if (!w->cap_stream) QA_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g;
+        QA_HIP(hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal));
+        st = enqueue_batch(w, w->cap_stream, n_diag, plan, V_dev, n_out_dev, nbar_out_dev,
+                           tune.blocks);
+        hipError_t ec = hipStreamEndCapture(w->cap_stream, &g);
+        if (st) return st;
+        if (ec != hipSuccess)
+            return fail(QA_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        ec = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ec != hipSuccess) {
+            w->graph = nullptr;
+            return fail(QA_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ec));
+        }
+        w->graph_key = key;
+    }
+    QA_HIP(hipGraphLaunch(w->graph, w->stream));
+    return read_stats(w, stats);
 }
 
 void qa_timing_enable(int on) { g_timing = on != 0; }
@@ -385,6 +596,11 @@ void qa_release(void *hip_stream)
     (void)hipFree(w->acc);
     for (auto &e : w->ev)
         for (auto &x : e) (void)hipEventDestroy(x);
+    (void)hipFree(w->bhdr);
+    (void)hipFree(w->bmats);
+    (void)hipFree(w->brecs);
+    if (w->graph) (void)hipGraphExecDestroy(w->graph);
+    if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
     delete w;
 }
 

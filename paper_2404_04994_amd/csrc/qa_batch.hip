@@ -1,0 +1,375 @@
+// qa_batch.hip -- a ragged batch of stability diagrams (different dot counts,
+// open and closed arrays, different temperatures) in one persistent launch,
+// the dataset-generation use the paper motivates (Sec. 1, Sec. 8).
+//
+//   k_prep_batch  one block per diagram: copies C_dd, C_gd and the solve
+//                 mode into a DiagRec and runs the same prologue as a single
+//                 diagram (A = C_dd^{-1} in FP64).
+//   k_batch       persistent: each wave takes 64-pixel work items from a
+//                 queue; a work item belongs to one diagram, so every lane of
+//                 the wave shares its dot count and candidate layout.  Lane =
+//                 pixel, and the whole path runs in registers: x_u = C_gd V,
+//                 the analytic minimum or the exact QP (Sec. 3.1), the
+//                 candidate set (Sec. 3.2), the argmin (Eq. argmin) and, when
+//                 kT > 0, the softargmin (Eq. softargmin) over the set, all
+//                 energies in FP64.  Nothing per pixel goes back to HBM except
+//                 the results.
+#include "qa_device.h"
+
+namespace qa {
+
+__global__ __launch_bounds__(64) void k_prep_batch(const BatchHdr *__restrict__ hdr,
+                                                   const double *__restrict__ mats,
+                                                   DiagRec *__restrict__ recs)
+{
+    __shared__ double L[kMaxDot * kMaxDot];
+    __shared__ double Ainv[kMaxDot * kMaxDot];
+    const BatchHdr h = hdr[blockIdx.x];
+    DiagRec *dr = recs + blockIdx.x;
+    const int n = h.n, g = h.g;
+    const double *cdd = mats + h.mat_off;
+    const double *cgd = cdd + n * n;
+    for (int e = threadIdx.x; e < kMaxDot * kMaxDot; e += blockDim.x) {
+        const int i = e / kMaxDot, j = e % kMaxDot;
+        dr->Cdd[e] = (i < n && j < n) ? cdd[i * n + j] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kMaxDot * kMaxGate; e += blockDim.x) {
+        const int i = e / kMaxGate, j = e % kMaxGate;
+        dr->Cgd[e] = (i < n && j < g) ? cgd[i * g + j] : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        dr->n = n;
+        dr->g = g;
+        dr->closed = h.closed;
+        dr->nhat = h.nhat;
+        dr->kT = h.kT;
+        dr->t = h.t;
+        dr->prec = 0;
+    }
+    __syncthreads();
+    prep_body(dr, L, Ainv);
+}
+
+hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *recs, int n_diag,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prep_batch, dim3(n_diag), dim3(64), 0, s, hdr, mats, recs);
+    return hipGetLastError();
+}
+
+// Dense box of n <= 8 dots (every dot free), walked by one lane.  With s the
+// raised dots and h(s) = 1/2 s^T A s from the diagram's table (LDS),
+//     U(n0 + s) - U(n0) = s . g0 + h(s)                       (Eq. free_energy)
+// The 2^n states are visited in blocks of sixteen Gray-code steps: inside a
+// block only dots 0..3 flip, the flipped dot and (for dots 0..2) its new value
+// are compile-time constants, and gray(16 o + k) = gray(16 o) ^ gray(k).
+// Pass 1 finds the smallest energy; pass 2 finds the lexicographically
+// smallest state at that energy (the rank brev(s)), the runner-up energy and,
+// for kT > 0, the Boltzmann sums (weights exp2 in FP32 of an FP64 argument,
+// relative error below 3e-6 for every weight above e^-60; sums in FP64).
+template <int NM>
+__device__ __forceinline__ int64_t dense_small(const double *__restrict__ sh,
+                                               const double (&g0)[NM], int n, int k, double kT,
+                                               bool soft, double &e1out, double &e2out,
+                                               uint32_t &s1out, double &Z, double (&sv)[NM])
+{
+    const int nb = n > 4 ? 1 << (n - 4) : 1;
+    const int kmax = n >= 4 ? 16 : 1 << n;
+    int64_t scored = 0;
+    double e1 = INFINITY;
+    for (int o = 0; o < nb; ++o) {
+        const uint32_t sb = ((uint32_t)o << 4) ^ ((uint32_t)o << 3);
+        const int par = o & 1;
+        const int pchi = __popc(sb >> 4);
+        double L = 0.0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+            if (sb >> i & 1u) L += g0[i];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const uint32_t gk = (uint32_t)(kk ^ (kk >> 1));
+            if (kk > 0) {
+                const int d = __builtin_ctz(kk);
+                if (d < 3) L += ((gk >> d) & 1u) ? g0[d] : -g0[d];
+                else L += par ? -g0[3] : g0[3];
+            }
+            if (kk < kmax) {
+                const bool valid = k < 0 || pchi + __popc((gk ^ ((uint32_t)par << 3)) & 15u) == k;
+                if (valid) {
+                    e1 = fmin(e1, L + sh[sb ^ gk]);
+                    ++scored;
+                }
+            }
+        }
+    }
+    const double c = soft ? 1.4426950408889634 / kT : 0.0;
+    uint32_t r1 = 0xFFFFFFFFu;
+    int neq = 0;
+    double e2 = INFINITY;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) sv[i] = 0.0;
+    Z = 0.0;
+    for (int o = 0; o < nb; ++o) {
+        const uint32_t sb = ((uint32_t)o << 4) ^ ((uint32_t)o << 3);
+        const uint32_t rb = __brev(sb);
+        const int par = o & 1;
+        const int pchi = __popc(sb >> 4);
+        double L = 0.0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+            if (sb >> i & 1u) L += g0[i];
+        float sblk = 0.0f, t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const uint32_t gk = (uint32_t)(kk ^ (kk >> 1));
+            if (kk > 0) {
+                const int d = __builtin_ctz(kk);
+                if (d < 3) L += ((gk >> d) & 1u) ? g0[d] : -g0[d];
+                else L += par ? -g0[3] : g0[3];
+            }
+            if (kk < kmax) {
+                const bool valid = k < 0 || pchi + __popc((gk ^ ((uint32_t)par << 3)) & 15u) == k;
+                if (valid) {
+                    const double e = L + sh[sb ^ gk];
+                    if (e == e1) {
+                        r1 = min(r1, rb ^ __brev(gk));
+                        ++neq;
+                    } else {
+                        e2 = fmin(e2, e);
+                    }
+                    if (soft) {
+                        const float w = exp2f((float)((e1 - e) * c));
+                        sblk += w;
+                        if (gk & 1u) t0 += w;
+                        if (gk & 2u) t1 += w;
+                        if (gk & 4u) t2 += w;
+                        if (gk & 8u) t3 += w;
+                    }
+                }
+            }
+        }
+        if (soft) {
+            Z += sblk;
+            sv[0] += t0;
+            if (NM > 1) sv[1] += t1;
+            if (NM > 2) sv[2] += t2;
+            if (NM > 3) sv[3] += par ? (double)(sblk - t3) : (double)t3;
+#pragma unroll
+            for (int i = 4; i < NM; ++i)
+                if (sb >> i & 1u) sv[i] += sblk;
+        }
+    }
+    e1out = e1;
+    e2out = neq > 1 ? e1 : e2;
+    s1out = __brev(r1);
+    return scored;
+}
+
+// one pixel, lane-sequential: returns the number of candidates scored
+template <int NM>
+__device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
+                                               const double *__restrict__ A,
+                                               const double *__restrict__ hs, bool closed,
+                                               const double *__restrict__ Vp,
+                                               int32_t *__restrict__ nout,
+                                               double *__restrict__ nbout, int &qp, int &fail,
+                                               int &dbl, int &gap)
+{
+    const int n = dr->n, g = dr->g;
+    double xu[NM], x[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        double s = 0.0;
+        if (i < n)
+            for (int j = 0; j < g; ++j) s += dr->Cgd[i * kMaxGate + j] * Vp[j];
+        xu[i] = s;
+    }
+    // analytic minimum first (Sec. 3.1.1), the QP only when it is negative
+    double lam = 0.0;
+    if (closed) {
+        double sx = 0.0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) sx += xu[i];
+        lam = ((double)dr->nhat - sx) / dr->one_c;
+    }
+    bool feasible = true;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        x[i] = (i < n) ? xu[i] + lam * dr->c[i] : 0.0;
+        feasible &= x[i] >= 0.0;
+    }
+    if (closed && dr->nhat == 0) {
+        qp = !feasible;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) x[i] = 0.0;
+        feasible = true;
+    }
+    if (!feasible) {
+        qp = 1;
+        const bool ok = closed ? qp_solve<NM, true>(dr, xu, x) : qp_solve<NM, false>(dr, xu, x);
+        fail = ok ? 0 : 1;
+    }
+    int n0[NM];
+    uint32_t fm;
+    int k;
+    const int flags = candidate_set<NM>(dr, closed, x, n0, fm, k);
+    dbl = (flags & 4) ? 1 : 0;
+    double g0[NM];
+    const double u0 = base_state<NM>(A, n, n0, xu, g0);
+    if (NM <= 8 && fm == (1u << n) - 1u) {
+        // dense box: table-driven walk
+        const bool soft = nbout != nullptr && dr->kT > 0.0;
+        double e1, e2, Z, sv[NM];
+        uint32_t s1;
+        const int64_t scored = dense_small<NM>(hs, g0, n, k, dr->kT, soft, e1, e2, s1, Z, sv);
+        gap = (e2 - e1 < 1e-9) ? 1 : 0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+            if (i < n) nout[i] = n0[i] + (int)(s1 >> i & 1u);
+        if (nbout) {
+#pragma unroll
+            for (int i = 0; i < NM; ++i)
+                if (i < n)
+                    nbout[i] = soft ? (double)n0[i] + sv[i] / Z
+                                    : (double)(n0[i] + (int)(s1 >> i & 1u));
+        }
+        return scored;
+    }
+    // any other set: argmin and runner-up with the y = A 1_s walk
+    const int m = __popc(fm);
+    const uint64_t pos = free_positions(fm);
+    const int steps = 1 << m;
+    double y[NM];
+    double e1 = INFINITY, e2 = INFINITY;
+    uint32_t s1 = 0;
+    int64_t scored = 0;
+    {
+        uint32_t s = 0;
+        int pc = 0;
+        walk_start<NM>(A, s, y);
+        for (int step = 0; step < steps; ++step) {
+            if (step) walk_flip<NM>(A, pos, step, s, pc, y);
+            if (k < 0 || pc == k) {
+                const double e = walk_energy<NM>(g0, y, u0, s);
+                ++scored;
+                if (better(e, s, e1, s1)) { e2 = e1; e1 = e; s1 = s; }
+                else if (e < e2) e2 = e;
+            }
+        }
+    }
+    gap = (e2 - e1 < 1e-9) ? 1 : 0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i)
+        if (i < n) nout[i] = n0[i] + (int)(s1 >> i & 1u);
+    if (nbout) {
+        const double kT = dr->kT;
+        if (kT > 0.0) {
+            double Z = 0.0, sv[NM];
+#pragma unroll
+            for (int i = 0; i < NM; ++i) sv[i] = 0.0;
+            uint32_t s = 0;
+            int pc = 0;
+            walk_start<NM>(A, s, y);
+            for (int step = 0; step < steps; ++step) {
+                if (step) walk_flip<NM>(A, pos, step, s, pc, y);
+                if (k < 0 || pc == k) {
+                    const double w = exp(-(walk_energy<NM>(g0, y, u0, s) - e1) / kT);
+                    Z += w;
+#pragma unroll
+                    for (int i = 0; i < NM; ++i)
+                        if (s >> i & 1u) sv[i] += w;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NM; ++i)
+                if (i < n) nbout[i] = (double)n0[i] + sv[i] / Z;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NM; ++i)
+                if (i < n) nbout[i] = (double)(n0[i] + (int)(s1 >> i & 1u));
+        }
+    }
+    return scored;
+}
+
+template <int NM>
+__global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
+                                              const DiagRec *__restrict__ recs, int n_diag,
+                                              int64_t tiles, const double *__restrict__ V,
+                                              int32_t *__restrict__ n_out,
+                                              double *__restrict__ nbar,
+                                              int64_t *__restrict__ counters)
+{
+    __shared__ double sA[kMaxDot * kMaxDot];
+    __shared__ double sh[256];
+    __shared__ int64_t sitem;
+    const int lane = threadIdx.x;
+    int64_t npix = 0, nqp = 0, nfail = 0, ndbl = 0, ngap = 0, ncand = 0;
+    for (;;) {
+        if (lane == 0) sitem = (int64_t)atomicAdd((unsigned long long *)&counters[C_WORK], 1ull);
+        __syncthreads();
+        const int64_t item = sitem;
+        if (item >= tiles) break;
+        // the diagram of this work item: last d with tile0 <= item
+        int lo = 0, hi = n_diag - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (hdr[mid].tile0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchHdr h = hdr[lo];
+        const DiagRec *dr = recs + lo;
+        for (int e = lane; e < kMaxDot * kMaxDot; e += 64) sA[e] = dr->A[e];
+        if (NM <= 8)
+            for (int e = lane; e < 256; e += 64) sh[e] = dr->hs[e];
+        __syncthreads();
+        const int64_t p = (item - h.tile0) * 64 + lane;
+        if (p < h.P) {
+            int qp = 0, fail = 0, dbl = 0, gap = 0;
+            ncand += batch_pixel<NM>(dr, sA, sh, h.closed != 0, V + h.v_off + p * h.g,
+                                     n_out + h.out_off + p * h.n,
+                                     nbar ? nbar + h.out_off + p * h.n : nullptr, qp, fail, dbl,
+                                     gap);
+            ++npix;
+            nqp += qp;
+            nfail += fail;
+            ndbl += dbl;
+            ngap += gap;
+        }
+        __syncthreads();  // sA and sitem are rewritten by the next item
+    }
+    // wave totals -> counters
+    npix = (int64_t)group_sum<6>((double)npix);
+    nqp = (int64_t)group_sum<6>((double)nqp);
+    nfail = (int64_t)group_sum<6>((double)nfail);
+    ndbl = (int64_t)group_sum<6>((double)ndbl);
+    ngap = (int64_t)group_sum<6>((double)ngap);
+    ncand = (int64_t)group_sum<6>((double)ncand);
+    if (lane == 0) {
+        block_add_counter(counters, C_PIXELS, npix);
+        block_add_counter(counters, C_QP, nqp);
+        block_add_counter(counters, C_QP_FAIL, nfail);
+        block_add_counter(counters, C_DOUBLED, ndbl);
+        block_add_counter(counters, C_GAP_1E9, ngap);
+        block_add_counter(counters, C_CANDIDATES, ncand);
+    }
+}
+
+hipError_t launch_batch(const BatchHdr *hdr, const DiagRec *recs, int n_diag, int64_t tiles,
+                        const double *V, int32_t *n_out, double *nbar, int64_t *counters,
+                        int max_dot, int blocks, hipStream_t s)
+{
+    if (blocks < 1) blocks = 1;
+    if (max_dot <= 4)
+        hipLaunchKernelGGL(k_batch<4>, dim3(blocks), dim3(64), 0, s, hdr, recs, n_diag, tiles, V,
+                           n_out, nbar, counters);
+    else if (max_dot <= 8)
+        hipLaunchKernelGGL(k_batch<8>, dim3(blocks), dim3(64), 0, s, hdr, recs, n_diag, tiles, V,
+                           n_out, nbar, counters);
+    else
+        hipLaunchKernelGGL(k_batch<16>, dim3(blocks), dim3(64), 0, s, hdr, recs, n_diag, tiles, V,
+                           n_out, nbar, counters);
+    return hipGetLastError();
+}
+
+}  // namespace qa

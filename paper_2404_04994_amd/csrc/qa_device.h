@@ -1,0 +1,402 @@
+// qa_device.h -- device helpers shared by the kernels of libqarray:
+// candidate sets (Sec. 3.2), the exact QP of Sec. 3.1.2, and the Gray-code
+// walk over a candidate set with FP64 energies (Eq. free_energy).
+#pragma once
+#include "qa_internal.h"
+
+#include <math.h>
+
+namespace qa {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pdep_mask(uint32_t c, uint32_t mask)
+{
+    // scatter the low bits of c onto the set bits of mask, in order
+    uint32_t s = 0;
+    for (int j = 0; mask; ++j) {
+        const uint32_t low = mask & (0u - mask);
+        if (c >> j & 1u) s |= low;
+        mask ^= low;
+    }
+    return s;
+}
+
+__device__ __forceinline__ bool better(double e, uint32_t s, double e1, uint32_t s1)
+{
+    // smaller energy; equal energies resolve to the lexicographically
+    // smallest charge vector (dot 0 most significant)
+    return e < e1 || (e == e1 && __brev(s) < __brev(s1));
+}
+
+__device__ __forceinline__ void block_add_counter(int64_t *counters, int which, int64_t v)
+{
+    if (v) atomicAdd((unsigned long long *)&counters[which], (unsigned long long)v);
+}
+
+// Candidate set of Sec. 3.2 for the continuous minimum x: base state n0,
+// mask of dots that take both roundings and, for closed arrays, the number k
+// of those dots raised by one (k = -1 for open arrays).  Returns the flags
+// (bit1: no admissible state even at t = 1, bit2: the threshold doubled).
+template <int NM>
+__device__ __forceinline__ int candidate_set(const DiagRec *__restrict__ dr, bool closed,
+                                             const double (&x)[NM], int (&n0)[NM],
+                                             uint32_t &fm, int &k)
+{
+    const int n = dr->n;
+    double t = dr->t;
+    int flags = 0;
+    k = -1;
+    for (int iter = 0; iter < 80; ++iter) {
+        fm = 0;
+        int sum0 = 0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            n0[i] = 0;
+            if (i < n) {
+                // the box starts at floor(x* + 1e-9): a continuous minimum on
+                // an integer (an active bound, a whole free charge) keeps that
+                // integer as its floor whatever its last rounded bit
+                const double f = floor(x[i] + 1e-9);
+                const double fr = x[i] - f;
+                const bool freed = (t >= 1.0) || (fabs(fr - 0.5) <= 0.5 * t);
+                n0[i] = (int)f + ((!freed && fr > 0.5) ? 1 : 0);
+                if (freed) fm |= 1u << i;
+                sum0 += n0[i];
+            }
+        }
+        if (!closed) break;
+        const int need = dr->nhat - sum0;
+        if (need >= 0 && need <= __popc(fm)) { k = need; break; }
+        if (t >= 1.0) {  // |sum x* - N_hat| < 1 makes this unreachable
+            k = need < 0 ? 0 : __popc(fm);
+            flags |= 2;
+            break;
+        }
+        t = (t > 0.0) ? fmin(1.0, 2.0 * t) : 1.0;
+        flags |= 4;
+    }
+    return flags;
+}
+
+// g0 = A (n0 - x_u) and U(n0) = 1/2 (n0 - x_u)^T g0 (Eq. free_energy)
+template <int NM>
+__device__ __forceinline__ double base_state(const double *__restrict__ A, int n,
+                                             const int (&n0)[NM], const double (&xu)[NM],
+                                             double (&g0)[NM])
+{
+    double z[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) z[i] = (i < n) ? (double)n0[i] - xu[i] : 0.0;
+    double u0 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NM; ++j) s += A[i * kMaxDot + j] * z[j];
+        g0[i] = s;
+        u0 += z[i] * s;
+    }
+    return 0.5 * u0;
+}
+
+// Cholesky solve of an SPD system held as a packed lower triangle, M fixed.
+template <int M>
+__device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2], double (&b)[M])
+{
+#define LIDX(i, j) ((i) * ((i) + 1) / 2 + (j))
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double d = a[LIDX(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d -= a[LIDX(j, k)] * a[LIDX(j, k)];
+        d = sqrt(d);
+        a[LIDX(j, j)] = d;
+        const double inv = 1.0 / d;
+#pragma unroll
+        for (int i = j + 1; i < M; ++i) {
+            double s = a[LIDX(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= a[LIDX(i, k)] * a[LIDX(j, k)];
+            a[LIDX(i, j)] = s * inv;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= a[LIDX(i, k)] * b[k];
+        b[i] = s / a[LIDX(i, i)];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = i + 1; k < M; ++k) s -= a[LIDX(k, i)] * b[k];
+        b[i] = s / a[LIDX(i, i)];
+    }
+#undef LIDX
+}
+
+// The QP of Sec. 3.1.2, min U(x) s.t. x >= 0 [and 1^T x = N_hat], in its KKT
+// form x = x_u + C_dd mu + lambda C_dd 1, mu >= 0, x >= 0, mu_i x_i = 0.
+// For an active set W (x_W = 0, mu zero off W) the unknowns (mu_W, lambda)
+// solve  [C_WW  c_W; c_W^T  1^T c] [mu_W; lambda] = [-x_u,W; N_hat - 1^T x_u]
+// (open arrays: the C_WW block alone).  The system is embedded in a fixed
+// (NM [+1])-size SPD matrix with identity rows for dots outside W, so all
+// indexing is static.  Primal-dual active-set update (Hintermueller, Ito and
+// Kunisch, SIAM J. Optim. 13, 2003): keep dots with mu > 0, add dots with
+// x < 0; stop when W repeats.  For open arrays C_dd is an M-matrix and W only
+// grows (Chandrasekaran's method), at most N rounds.  Returns false when the
+// iteration did not settle (x is then the last iterate, clipped at 0).
+template <int NM, bool CLOSED>
+__device__ bool qp_solve(const DiagRec *__restrict__ dr, const double (&xu)[NM], double (&x)[NM])
+{
+    constexpr int M = NM + (CLOSED ? 1 : 0);
+    const int n = dr->n;
+    double sx = 0.0, scale = 1.0, mu[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        sx += xu[i];
+        scale = fmax(scale, fabs(xu[i]));
+    }
+    const double tol = 1e-13 * scale;
+    const double lam0 = CLOSED ? ((double)dr->nhat - sx) / dr->one_c : 0.0;
+    uint32_t W = 0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i)
+        if (i < n && xu[i] + lam0 * dr->c[i] < 0.0) W |= 1u << i;
+    bool converged = false;
+    for (int round = 0; round < 4 * NM + 4; ++round) {
+        double a[M * (M + 1) / 2], b[M];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            const bool wi = W >> i & 1u;
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                const bool wj = W >> j & 1u;
+                double v = (wi && wj) ? dr->Cdd[i * kMaxDot + j] : 0.0;
+                if (i == j && !wi) v = 1.0;
+                a[i * (i + 1) / 2 + j] = v;
+            }
+            b[i] = wi ? -xu[i] : 0.0;
+        }
+        if (CLOSED) {
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+                a[NM * (NM + 1) / 2 + j] = (W >> j & 1u) ? dr->c[j] : 0.0;
+            a[NM * (NM + 1) / 2 + NM] = dr->one_c;
+            b[M - 1] = (double)dr->nhat - sx;
+        }
+        chol_solve<M>(a, b);
+        const double lam = CLOSED ? b[M - 1] : 0.0;
+        uint32_t Wn = 0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) mu[i] = (W >> i & 1u) ? b[i] : 0.0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            double s = xu[i] + lam * dr->c[i];
+#pragma unroll
+            for (int j = 0; j < NM; ++j) s += dr->Cdd[i * kMaxDot + j] * mu[j];
+            x[i] = (W >> i & 1u) ? 0.0 : s;
+            if (i < n) {
+                if (W >> i & 1u) {
+                    if (mu[i] > -tol) Wn |= 1u << i;
+                } else if (x[i] < -tol) {
+                    Wn |= 1u << i;
+                }
+            }
+        }
+        if (Wn == W) { converged = true; break; }
+        W = Wn;
+    }
+#pragma unroll
+    for (int i = 0; i < NM; ++i) x[i] = (i < n) ? fmax(x[i], 0.0) : 0.0;
+    return converged;
+}
+
+// ---------------------------------------------------------------------------
+// candidate walk shared by the FP64 kernels.
+//
+// A pixel's candidates are n0 + 1_s for s within its free mask (m dots);
+// a group of G = 2^LG lanes splits the 2^m compressed indices into chunks of
+// consecutive integers and walks each chunk in Gray-code order, so that one
+// dot flips per step and the flipped dot is the same in every lane of the
+// group.  With y = A 1_s maintained incrementally,
+//   U(n0 + 1_s) = U(n0) + sum_{i in s} (g0_i + y_i / 2)      (Eq. free_energy)
+// ---------------------------------------------------------------------------
+struct WalkState {
+    uint32_t s;
+    int pc;
+};
+
+template <int NM>
+__device__ __forceinline__ double walk_energy(const double (&g0)[NM], const double (&y)[NM],
+                                              double u0, uint32_t s)
+{
+    double e = u0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i)
+        if (s >> i & 1u) e += g0[i] + 0.5 * y[i];
+    return e;
+}
+
+template <int NM>
+__device__ __forceinline__ void walk_start(const double *__restrict__ sA, uint32_t s,
+                                           double (&y)[NM])
+{
+#pragma unroll
+    for (int i = 0; i < NM; ++i) y[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NM; ++j)
+        if (s >> j & 1u) {
+#pragma unroll
+            for (int i = 0; i < NM; ++i) y[i] += sA[j * kMaxDot + i];
+        }
+}
+
+template <int NM>
+__device__ __forceinline__ void walk_flip(const double *__restrict__ sA, uint64_t pos, int step,
+                                          uint32_t &s, int &pc, double (&y)[NM])
+{
+    const int j = __ffs(step) - 1;
+    const int d = (int)((pos >> (4 * j)) & 15u);
+    const uint32_t bit = 1u << d;
+    const double sg = (s & bit) ? -1.0 : 1.0;
+    s ^= bit;
+    pc += (s & bit) ? 1 : -1;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) y[i] += sg * sA[d * kMaxDot + i];
+}
+
+__device__ __forceinline__ uint64_t free_positions(uint32_t fm)
+{
+    uint64_t pos = 0;
+    for (int j = 0; fm; ++j) {
+        pos |= (uint64_t)(__ffs(fm) - 1) << (4 * j);
+        fm &= fm - 1;
+    }
+    return pos;
+}
+
+template <int LG>
+__device__ __forceinline__ double group_min(double v)
+{
+#pragma unroll
+    for (int off = (1 << LG) / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 1 << LG));
+    return v;
+}
+
+template <int LG>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int off = (1 << LG) / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 1 << LG);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// K0: per-diagram prologue
+// ---------------------------------------------------------------------------
+// Prologue of one diagram, run by one 64-thread block: A = C_dd^{-1} by
+// Cholesky (FP64), C_dd 1, 1^T C_dd 1, sum|A|/2 and, for n >= 9, the tables of
+// the matrix-core scorer.  L and Ainv are kMaxDot^2 doubles of LDS.
+__device__ inline void prep_body(DiagRec *dr, double *L, double *Ainv)
+{
+    const int n = dr->n;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        // Cholesky C_dd = L L^T (the host has checked positive definiteness)
+        for (int j = 0; j < n; ++j) {
+            double d = dr->Cdd[j * kMaxDot + j];
+            for (int k = 0; k < j; ++k) d -= L[j * kMaxDot + k] * L[j * kMaxDot + k];
+            const double ljj = sqrt(d);
+            L[j * kMaxDot + j] = ljj;
+            for (int i = j + 1; i < n; ++i) {
+                double s = dr->Cdd[i * kMaxDot + j];
+                for (int k = 0; k < j; ++k) s -= L[i * kMaxDot + k] * L[j * kMaxDot + k];
+                L[i * kMaxDot + j] = s / ljj;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < n) {
+        // column tid of A: L y = e_tid, then L^T a = y
+        double y[kMaxDot], a[kMaxDot];
+        for (int i = 0; i < n; ++i) {
+            double s = (i == tid) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= L[i * kMaxDot + k] * y[k];
+            y[i] = s / L[i * kMaxDot + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < n; ++k) s -= L[k * kMaxDot + i] * a[k];
+            a[i] = s / L[i * kMaxDot + i];
+        }
+        for (int i = 0; i < n; ++i) Ainv[i * kMaxDot + tid] = a[i];
+    }
+    __syncthreads();
+    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) {
+        const int i = e / kMaxDot, j = e % kMaxDot;
+        double v = 0.0;
+        if (i < n && j < n) v = 0.5 * (Ainv[i * kMaxDot + j] + Ainv[j * kMaxDot + i]);
+        dr->A[e] = v;
+        Ainv[e] = v;  // exactly symmetric copy for the tables below
+    }
+    __syncthreads();
+    if (tid < kMaxDot) {
+        double s = 0.0;
+        if (tid < n)
+            for (int j = 0; j < n; ++j) s += dr->Cdd[tid * kMaxDot + j];
+        dr->c[tid] = s;
+    }
+    if (tid == 0) {
+        double s = 0.0, sa = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                s += dr->Cdd[i * kMaxDot + j];
+                sa += fabs(Ainv[i * kMaxDot + j]);
+            }
+        dr->one_c = s;
+        dr->sumabs = (float)(0.5 * sa);
+    }
+    // tables of the matrix-core scorer: low part = dots 0..7, high = 8..n-1
+    if (n >= 9) {
+        const int nh = n - 8;
+        for (int e = tid; e < 16 * 8; e += blockDim.x) {
+            const int r = e / 8, i = e % 8;
+            double t1 = 0.0, t2 = 0.0;
+            for (int j = 0; j < 4; ++j) {
+                if ((r >> j & 1) && j < nh) t1 += Ainv[i * kMaxDot + 8 + j];
+                if ((r >> j & 1) && j + 4 < nh) t2 += Ainv[i * kMaxDot + 12 + j];
+            }
+            dr->T1[r][i] = (float)t1;
+            dr->T2[r][i] = (float)t2;
+        }
+        for (int e = tid; e < 256; e += blockDim.x) {
+            double hh = 0.0, hl = 0.0;
+            for (int a = 0; a < 8; ++a)
+                for (int b = 0; b < 8; ++b) {
+                    if ((e >> a & 1) && (e >> b & 1)) {
+                        hl += Ainv[a * kMaxDot + b];
+                        if (a < nh && b < nh) hh += Ainv[(8 + a) * kMaxDot + 8 + b];
+                    }
+                }
+            dr->hlo[e] = (float)(0.5 * hl);
+            dr->Hhi[e] = (e < (1 << nh)) ? (float)(0.5 * hh) : 1e30f;
+        }
+    } else {
+        // whole-box table of the lane walk: h(s) = 1/2 s^T A s, s < 2^n
+        for (int e = tid; e < 256; e += blockDim.x) {
+            double h = 0.0;
+            if (e < (1 << n))
+                for (int a = 0; a < n; ++a)
+                    for (int b = 0; b < n; ++b)
+                        if ((e >> a & 1) && (e >> b & 1)) h += Ainv[a * kMaxDot + b];
+            dr->hs[e] = 0.5 * h;
+        }
+    }
+}
+
+}  // namespace qa

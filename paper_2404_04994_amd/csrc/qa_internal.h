@@ -31,6 +31,7 @@ enum Counter {
     C_QP_LIST = 7,      // length of the QP pixel list
     C_FLAG_LIST = 8,    // length of the full FP64 re-score list
     C_BAND_OVERFLOW = 9,
+    C_WORK = 10,        // work-queue cursor of the batched kernel
     C_NUM = 16
 };
 
@@ -51,6 +52,7 @@ struct alignas(16) DiagRec {
     float hlo[256];               // 1/2 b_lo^T A_LL b_lo
     float sumabs;                 // sum |A_ij| / 2, bound used by the error band
     float pad1[3];
+    double hs[256];               // n <= 8: 1/2 s^T A s for every s in {0,1}^n
 };
 
 struct alignas(8) PixRec {
@@ -69,6 +71,17 @@ struct alignas(8) SavedRec {
     int16_t n0[kMaxDot];
     uint32_t free;
     int32_t k;
+};
+
+// one diagram of a ragged batch, as uploaded by the host (work order)
+struct alignas(8) BatchHdr {
+    int32_t n, g, closed, nhat;
+    double kT, t;
+    int64_t v_off;    // element offset of the diagram's P x G voltages
+    int64_t out_off;  // element offset of its P x N outputs
+    int64_t P;        // pixels
+    int64_t mat_off;  // offset of C_dd (n x n) then C_gd (n x g) in the matrix buffer
+    int64_t tile0;    // first 64-pixel work item of the diagram
 };
 
 // -------------------------------------------------------------------------
@@ -100,5 +113,12 @@ hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P,
 hipError_t launch_soft_bwd_final(const DiagRec *dr, const double *accA, const double *accG,
                                  const double *accU, double *grad_cdd, double *grad_cgd,
                                  hipStream_t s);
+// ragged batch (qa_batch.hip): prologue of every diagram, then one persistent
+// kernel over all 64-pixel work items
+hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *recs, int n_diag,
+                             hipStream_t s);
+hipError_t launch_batch(const BatchHdr *hdr, const DiagRec *recs, int n_diag, int64_t tiles,
+                        const double *V, int32_t *n_out, double *nbar, int64_t *counters,
+                        int max_dot, int blocks, hipStream_t s);
 
 }  // namespace qa

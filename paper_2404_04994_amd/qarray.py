@@ -205,6 +205,56 @@ def soft_charge_autograd(cdd, cgd, V, kT, closed=False, nhat=0, t=1.0):
     return SoftCharge.apply(cdd, cgd, V, kT, closed, nhat, t)
 
 
+class Batch:
+    """A ragged batch of diagrams packed for qa_ground_state_batched: the
+    problem array (host), the concatenated voltages (device) and the offsets.
+    Outputs: n (int32) and nbar (FP64) flat device tensors; rows of diagram d
+    start at out_offsets[d] elements."""
+
+    def __init__(self, diagrams, device="cuda"):
+        self.diagrams = list(diagrams)
+        nd = len(self.diagrams)
+        self.problems = (Problem * nd)()
+        self._keep = []
+        v_off, p_cnt, o_off = [], [], []
+        vo = oo = 0
+        for i, d in enumerate(self.diagrams):
+            pb, keep = make_problem(d.cdd, d.cgd, d.closed, d.nhat, d.kT, d.t, "fp64")
+            self.problems[i] = pb
+            self._keep.append(keep)
+            v_off.append(vo)
+            p_cnt.append(d.P)
+            o_off.append(oo)
+            vo += d.P * d.n_gate
+            oo += d.P * d.n_dot
+        self.v_offsets = np.array(v_off, np.int64)
+        self.pix_counts = np.array(p_cnt, np.int64)
+        self.out_offsets = np.array(o_off, np.int64)
+        self.V = torch.as_tensor(np.concatenate([np.ascontiguousarray(d.V, np.float64).ravel()
+                                                 for d in self.diagrams]), device=device)
+        self.n = torch.empty(max(oo, 1), dtype=torch.int32, device=device)
+        self.nbar = torch.empty(max(oo, 1), dtype=torch.float64, device=device)
+        self.pixels = int(self.pix_counts.sum())
+
+    def run(self, with_nbar=True, stream=None, stats=False):
+        lib = load()
+        i64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+        st = Stats() if stats else None
+        _check(lib.qa_ground_state_batched(
+            self.problems, len(self.diagrams), C.c_void_p(self.V.data_ptr()), i64(self.v_offsets),
+            i64(self.pix_counts), i64(self.out_offsets), C.c_void_p(self.n.data_ptr()),
+            C.c_void_p(self.nbar.data_ptr()) if with_nbar else None,
+            C.byref(st) if st else None, _stream(stream)))
+        return st.as_dict() if stats else None
+
+    def result(self, d):
+        """(n, nbar) of diagram d as host arrays (P_d x N_d)."""
+        dg = self.diagrams[d]
+        o, k = int(self.out_offsets[d]), dg.P * dg.n_dot
+        return (self.n[o:o + k].view(dg.P, dg.n_dot).cpu().numpy(),
+                self.nbar[o:o + k].view(dg.P, dg.n_dot).cpu().numpy())
+
+
 def timing_enable(on: bool = True):
     load().qa_timing_enable(1 if on else 0)
 

@@ -103,3 +103,26 @@ def test_empty_input_is_a_noop(qa):
 def test_saved_bytes(qa):
     assert qa.saved_bytes(0, 4) == 0
     assert qa.saved_bytes(10, 4) == 10 * qa.saved_bytes(1, 4) > 0
+
+
+def test_batched_validation(qa):
+    lib = qa.load()
+    i64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
+    probs = (qa.Problem * 2)()
+    pa, ka = qa.make_problem(GOOD_CDD, GOOD_CGD)
+    pbad, kb = qa.make_problem(np.array([[1.0, -2.0], [-2.0, 1.0]]), GOOD_CGD)
+    probs[0], probs[1] = pa, pbad
+    off = np.zeros(2, np.int64)
+    cnt = np.array([4, 4], np.int64)
+    assert lib.qa_ground_state_batched(probs, 0, None, None, None, None, None, None, None,
+                                       None) == 0
+    st = lib.qa_ground_state_batched(probs, 2, C.c_void_p(16), i64(off), i64(cnt), i64(off),
+                                     C.c_void_p(16), None, None, None)
+    assert st == 4 and "diagram 1" in lib.qa_last_error().decode()
+    probs[1] = pa
+    cnt[1] = -1
+    st = lib.qa_ground_state_batched(probs, 2, C.c_void_p(16), i64(off), i64(cnt), i64(off),
+                                     C.c_void_p(16), None, None, None)
+    assert st == 2
+    assert lib.qa_ground_state_batched(probs, 2, C.c_void_p(16), None, i64(cnt), i64(off),
+                                       C.c_void_p(16), None, None, None) == 1
