@@ -186,6 +186,13 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
  * of each stage (ms_out[3]) over the calls recorded since the reset and the
  * number of calls (at most 4096 are kept).  Off by default. */
 void qa_timing_enable(int on);
+
+/* Launch mode.  With graphs on (the default, or QA_GRAPHS=0 in the
+ * environment to start with them off) each call replays a hipGraph captured
+ * for its launch shape and buffers (captured on first use; the per-call
+ * inputs are copied before the replay); off, every kernel is launched
+ * directly.  Results are identical.  Stage timing always launches directly. */
+void qa_graphs_enable(int on);
 void qa_timing_reset(void *hip_stream);
 qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out);
 

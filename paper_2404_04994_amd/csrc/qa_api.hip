@@ -70,6 +70,13 @@ struct Workspace {
     hipStream_t cap_stream = nullptr;   // private stream used for graph capture
     hipGraphExec_t graph = nullptr;
     std::vector<int64_t> graph_key;
+    // single-diagram calls: pinned staging ring for the uploaded inputs and
+    // the graphs of recent launch shapes
+    static constexpr int kRing = 8;
+    DiagRec *stage = nullptr;           // kRing pinned host records
+    hipEvent_t stage_ev[kRing] = {};
+    int stage_next = 0;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
 };
 
 // autotuned launch shape of the batched kernel, per batch signature
@@ -129,6 +136,7 @@ qa_status grow(Workspace *w, T *&ptr, int64_t &cap, int64_t need)
 
 qa_status get_ws(hipStream_t stream, Workspace **out)
 {
+    read_env();
     int dev = 0;
     QA_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_mu);
@@ -215,22 +223,115 @@ void fill_diag(const qa_problem *pb, DiagRec *h)
     }
 }
 
-// prologue + setup + QP for one diagram, shared by the entry points
-qa_status run_setup(Workspace *w, const qa_problem *pb, const double *V, int64_t P)
+// Upload the inputs of a diagram (header, C_dd, C_gd) through a ring of
+// pinned host records, so the copy is asynchronous and the host record is
+// not reused before its copy has run.
+qa_status upload_diag(Workspace *w, const qa_problem *pb)
+{
+    if (!w->stage) {
+        if (hipHostMalloc((void **)&w->stage, sizeof(DiagRec) * Workspace::kRing) != hipSuccess) {
+            w->stage = nullptr;
+            return fail(QA_E_WORKSPACE, "hipHostMalloc of the staging ring failed");
+        }
+        for (auto &e : w->stage_ev) QA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    const int slot = w->stage_next;
+    w->stage_next = (slot + 1) % Workspace::kRing;
+    QA_HIP(hipEventSynchronize(w->stage_ev[slot]));
+    fill_diag(pb, &w->stage[slot]);
+    QA_HIP(hipMemcpyAsync(w->dr, &w->stage[slot], kDiagInputBytes, hipMemcpyHostToDevice,
+                          w->stream));
+    QA_HIP(hipEventRecord(w->stage_ev[slot], w->stream));
+    return QA_OK;
+}
+
+qa_status grow_single(Workspace *w, int64_t P)
 {
     qa_status st;
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
     if ((st = grow(w, w->pr, w->pr_cap, P))) return st;
     if ((st = grow(w, w->qp_list, w->qp_cap, P))) return st;
     if ((st = grow(w, w->flag_list, w->flag_cap, P))) return st;
-    DiagRec h;
-    fill_diag(pb, &h);
-    QA_HIP(launch_zero_i64(w->counters, C_NUM, w->stream));
-    QA_HIP(hipMemcpyAsync(w->dr, &h, sizeof(DiagRec), hipMemcpyHostToDevice, w->stream));
-    QA_HIP(launch_prep(w->dr, 1, w->stream));
+    return QA_OK;
+}
+
+bool use_matrix_cores(const qa_problem *pb)
+{
+    return pb->precision != QA_PREC_FP64 && pb->threshold >= 1.0 && pb->n_dot >= 9 &&
+           pb->mode == QA_OPEN;
+}
+
+// The device work of one single-diagram call on stream s (inputs already in
+// w->dr): counters, prologue, setup, QP, then either the T = 0 scoring
+// (n_out) or the softargmin (nbar, saved).  ev: optional stage events.
+qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, const double *V,
+                         int64_t P, int32_t *n_out, double *nbar, SavedRec *saved,
+                         std::array<hipEvent_t, 4> *ev)
+{
     const bool closed = pb->mode == QA_CLOSED;
-    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, w->stream));
-    QA_HIP(launch_qp(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, w->stream));
+    if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
+    QA_HIP(launch_zero_i64(w->counters, C_NUM, s));
+    QA_HIP(launch_prep(w->dr, 1, s));
+    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, s));
+    QA_HIP(launch_qp(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, s));
+    if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
+    if (nbar) {
+        QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
+        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
+    } else if (use_matrix_cores(pb)) {
+        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, n_out, w->flag_list,
+                                 w->counters, pb->n_dot, s));
+        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
+        QA_HIP(launch_score_fp64(w->dr, w->pr, P, w->flag_list, w->counters + C_FLAG_LIST, n_out,
+                                 w->counters, pb->n_dot, s));
+    } else {
+        QA_HIP(launch_score_fp64(w->dr, w->pr, P, nullptr, nullptr, n_out, w->counters,
+                                 pb->n_dot, s));
+        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
+    }
+    if (ev) QA_HIP(hipEventRecord((*ev)[3], s));
+    return QA_OK;
+}
+
+// Run a single-diagram call: with stage timing on, direct launches with
+// events; otherwise replay (or capture) the graph of this launch shape.
+qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_t P,
+                     int32_t *n_out, double *nbar, SavedRec *saved)
+{
+    qa_status st;
+    if ((st = grow_single(w, P))) return st;
+    if ((st = upload_diag(w, pb))) return st;
+    std::array<hipEvent_t, 4> *ev = timing_slot(w);
+    if (ev || !g_graphs) return enqueue_single(w, w->stream, pb, V, P, n_out, nbar, saved, ev);
+    const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + pb->precision : 1);
+    std::vector<int64_t> key = {pb->n_dot, pb->mode, path, P, (int64_t)(uintptr_t)V,
+                                (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
+                                (int64_t)(uintptr_t)saved, (int64_t)(uintptr_t)w->dr,
+                                (int64_t)(uintptr_t)w->pr, (int64_t)(uintptr_t)w->qp_list,
+                                (int64_t)(uintptr_t)w->flag_list};
+    auto it = w->graphs.find(key);
+    if (it == w->graphs.end()) {
+        if (w->graphs.size() >= 16) {
+            QA_HIP(hipStreamSynchronize(w->stream));
+            for (auto &kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+            w->graphs.clear();
+        }
+        if (!w->cap_stream) QA_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g;
+        QA_HIP(hipStreamBeginCapture(w->cap_stream, hipStreamCaptureModeThreadLocal));
+        st = enqueue_single(w, w->cap_stream, pb, V, P, n_out, nbar, saved, nullptr);
+        hipError_t ec = hipStreamEndCapture(w->cap_stream, &g);
+        if (st) return st;
+        if (ec != hipSuccess)
+            return fail(QA_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        hipGraphExec_t exec;
+        ec = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ec != hipSuccess)
+            return fail(QA_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ec));
+        it = w->graphs.emplace(key, exec).first;
+    }
+    QA_HIP(hipGraphLaunch(it->second, w->stream));
     return QA_OK;
 }
 
@@ -251,12 +352,6 @@ qa_status read_stats(Workspace *w, qa_stats *stats)
     return QA_OK;
 }
 
-bool use_matrix_cores(const qa_problem *pb)
-{
-    return pb->precision != QA_PREC_FP64 && pb->threshold >= 1.0 && pb->n_dot >= 9 &&
-           pb->mode == QA_OPEN;
-}
-
 }  // namespace
 
 extern "C" {
@@ -275,22 +370,7 @@ qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P
     if (!V_dev || !n_out_dev) return fail(QA_E_NULL, "V_dev or n_out_dev is NULL");
     Workspace *w;
     if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
-    std::array<hipEvent_t, 4> *ev = timing_slot(w);
-    if (ev) QA_HIP(hipEventRecord((*ev)[0], w->stream));
-    if ((st = run_setup(w, prob, V_dev, P))) return st;
-    if (ev) QA_HIP(hipEventRecord((*ev)[1], w->stream));
-    if (use_matrix_cores(prob)) {
-        QA_HIP(launch_score_mfma(w->dr, w->pr, P, prob->precision, n_out_dev, w->flag_list,
-                                 w->counters, prob->n_dot, w->stream));
-        if (ev) QA_HIP(hipEventRecord((*ev)[2], w->stream));
-        QA_HIP(launch_score_fp64(w->dr, w->pr, P, w->flag_list, w->counters + C_FLAG_LIST,
-                                 n_out_dev, w->counters, prob->n_dot, w->stream));
-    } else {
-        QA_HIP(launch_score_fp64(w->dr, w->pr, P, nullptr, nullptr, n_out_dev, w->counters,
-                                 prob->n_dot, w->stream));
-        if (ev) QA_HIP(hipEventRecord((*ev)[2], w->stream));
-    }
-    if (ev) QA_HIP(hipEventRecord((*ev)[3], w->stream));
+    if ((st = run_single(w, prob, V_dev, P, n_out_dev, nullptr, nullptr))) return st;
     return read_stats(w, stats);
 }
 
@@ -314,9 +394,8 @@ qa_status qa_soft_charge(const qa_problem *prob, const double *V_dev, int64_t P,
     if (!V_dev || !nbar_out_dev) return fail(QA_E_NULL, "V_dev or nbar_out_dev is NULL");
     Workspace *w;
     if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
-    if ((st = run_setup(w, prob, V_dev, P))) return st;
-    QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar_out_dev, (SavedRec *)saved_dev, w->counters,
-                           prob->n_dot, w->stream));
+    if ((st = run_single(w, prob, V_dev, P, nullptr, nbar_out_dev, (SavedRec *)saved_dev)))
+        return st;
     return read_stats(w, stats);
 }
 
@@ -339,9 +418,7 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
     const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + 4096;
     if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
-    DiagRec h;
-    fill_diag(prob, &h);
-    QA_HIP(hipMemcpyAsync(w->dr, &h, sizeof(DiagRec), hipMemcpyHostToDevice, w->stream));
+    if ((st = upload_diag(w, prob))) return st;
     QA_HIP(launch_prep(w->dr, 1, w->stream));
     double *accA = w->acc, *accG = accA + kMaxDot * kMaxDot, *accU = accG + kMaxDot * kMaxGate;
     QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, accA, accG,
@@ -546,6 +623,12 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
 
 void qa_timing_enable(int on) { g_timing = on != 0; }
 
+void qa_graphs_enable(int on)
+{
+    read_env();
+    g_graphs = on != 0;
+}
+
 void qa_timing_reset(void *hip_stream)
 {
     Workspace *w;
@@ -600,6 +683,10 @@ void qa_release(void *hip_stream)
     (void)hipFree(w->bmats);
     (void)hipFree(w->brecs);
     if (w->graph) (void)hipGraphExecDestroy(w->graph);
+    for (auto &kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (w->stage) (void)hipHostFree(w->stage);
+    for (auto &e : w->stage_ev)
+        if (e) (void)hipEventDestroy(e);
     if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
     delete w;
 }

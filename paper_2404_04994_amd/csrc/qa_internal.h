@@ -36,14 +36,16 @@ enum Counter {
 };
 
 struct alignas(16) DiagRec {
+    // inputs (written by the host, or by k_prep_batch): everything up to Cgd
     int32_t n, g, closed, nhat;
     double kT, t;
     int32_t prec, pad0;
+    double Cdd[kMaxDot * kMaxDot];
+    double Cgd[kMaxDot * kMaxGate];
+    // computed by the prologue
     double one_c;                 // 1^T C_dd 1
     double c[kMaxDot];            // C_dd 1
-    double Cdd[kMaxDot * kMaxDot];
     double A[kMaxDot * kMaxDot];  // C_dd^{-1}
-    double Cgd[kMaxDot * kMaxGate];
     // matrix-core tables (dense box, n >= 9): low part = dots 0..7,
     // high part = dots 8..n-1; see qa_mfma.hip
     float T1[16][8];              // A_LH b_hi for the 4 row bits of the high index
@@ -54,6 +56,9 @@ struct alignas(16) DiagRec {
     float pad1[3];
     double hs[256];               // n <= 8: 1/2 s^T A s for every s in {0,1}^n
 };
+
+// bytes of a DiagRec the host uploads (the inputs)
+constexpr size_t kDiagInputBytes = offsetof(DiagRec, one_c);
 
 struct alignas(8) PixRec {
     double g0[kMaxDot];   // A (n0 - x_u)

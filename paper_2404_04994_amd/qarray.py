@@ -22,7 +22,7 @@ STATUS = {0: "QA_OK", 1: "QA_E_NULL", 2: "QA_E_SHAPE", 3: "QA_E_NOT_SYMMETRIC", 
           5: "QA_E_RANGE", 6: "QA_E_UNSUPPORTED", 7: "QA_E_WORKSPACE", 8: "QA_E_DEVICE"}
 EXPORTS = ("qa_ground_state", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
            "qa_ground_state_batched", "qa_last_error", "qa_release", "qa_version",
-           "qa_timing_enable", "qa_timing_reset", "qa_timing_sum")
+           "qa_timing_enable", "qa_timing_reset", "qa_timing_sum", "qa_graphs_enable")
 
 
 class QArrayError(RuntimeError):
@@ -70,6 +70,7 @@ def load():
         lib.qa_version.restype = C.c_char_p
         lib.qa_release.argtypes = [vp]
         lib.qa_timing_enable.argtypes = [C.c_int]
+        lib.qa_graphs_enable.argtypes = [C.c_int]
         lib.qa_timing_reset.argtypes = [vp]
         lib.qa_timing_sum.argtypes = [vp, C.POINTER(C.c_double), i64p]
         lib.qa_timing_sum.restype = C.c_int
@@ -253,6 +254,10 @@ class Batch:
         o, k = int(self.out_offsets[d]), dg.P * dg.n_dot
         return (self.n[o:o + k].view(dg.P, dg.n_dot).cpu().numpy(),
                 self.nbar[o:o + k].view(dg.P, dg.n_dot).cpu().numpy())
+
+
+def graphs_enable(on: bool = True):
+    load().qa_graphs_enable(1 if on else 0)
 
 
 def timing_enable(on: bool = True):

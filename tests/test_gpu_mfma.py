@@ -97,3 +97,29 @@ def test_ragged_pixel_count(qa, oracle):
     for P in (1, 5, 63, 1001):
         sub = W.Diagram(d.cdd, d.cgd, d.V[:P])
         compare(qa, oracle, sub, "bf16x3")
+
+
+def test_graph_replays_match_eager(qa, oracle):
+    """Replays of the captured graph, with other eager work and waits between
+    them, give the eager result every time (single-diagram and soft paths)."""
+    d = W.grid4x4(206, npix=24)
+    c = W.chain4(131, npix=30)
+    V = torch.as_tensor(d.V).cuda()
+    Vc = torch.as_tensor(c.V).cuda()
+    qa.graphs_enable(False)
+    ref = qa.ground_state(d.cdd, d.cgd, V, precision="bf16x3").cpu()
+    ref_soft, _ = qa.soft_charge(c.cdd, c.cgd, Vc, 0.02)
+    ref_soft = ref_soft.cpu()
+    qa.graphs_enable(True)
+    out = torch.empty_like(ref).cuda()
+    for i in range(5):
+        qa.ground_state(d.cdd, d.cgd, V, precision="bf16x3", out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out.cpu(), ref), i
+        qa.graphs_enable(False)
+        qa.ground_state(c.cdd, c.cgd, Vc)           # eager work between replays
+        torch.cuda.synchronize()
+        qa.graphs_enable(True)
+        nb, _ = qa.soft_charge(c.cdd, c.cgd, Vc, 0.02)
+        torch.cuda.synchronize()
+        assert torch.equal(nb.cpu(), ref_soft), i

@@ -197,3 +197,36 @@ def test_soft_backward_matches_oracle(qa, oracle, closed):
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
         say("grad", name, "rel err %.3e" % rel)
         assert rel <= 1e-9
+
+
+@pytest.mark.parametrize("t", [2 / 3, 0.5, 1 / 3])
+def test_grid16_thresholded(qa, oracle, t):
+    """The 16-dot array with the thresholded candidate sets of Sec. 3.2.2."""
+    d = W.grid4x4(200, npix=30, t=t)
+    check_gs(qa, oracle, d.cdd, d.cgd, d.V, t=t)
+
+
+def test_max_gates_and_dots(qa, oracle):
+    """n_gate = 32 (the largest the library takes) and a closed 12-dot array."""
+    rng = np.random.default_rng(77)
+    cdd = np.diag(rng.uniform(1.0, 1.4, 5))
+    for i in range(4):
+        cdd[i, i + 1] = cdd[i + 1, i] = -rng.uniform(0.1, 0.3)
+    cgd = rng.uniform(0.0, 0.2, (5, 32))
+    V = rng.uniform(-5, 25, (700, 32))
+    check_gs(qa, oracle, cdd, cgd, V)
+    n = 12
+    c12 = np.diag(rng.uniform(1.0, 1.4, n))
+    for i in range(n - 1):
+        c12[i, i + 1] = c12[i + 1, i] = -rng.uniform(0.1, 0.3)
+    g12 = np.diag(rng.uniform(0.5, 1.0, n))
+    V12 = rng.uniform(-1, 3, (300, n))
+    check_gs(qa, oracle, c12, g12, V12, closed=True, nhat=9)
+    check_gs(qa, oracle, c12, g12, V12, closed=True, nhat=9, t=0.5)
+
+
+def test_empty_input(qa):
+    d = W.chain4(100, npix=4)
+    V = torch.empty((0, 5), dtype=torch.float64, device="cuda")
+    n, st = qa.ground_state(d.cdd, d.cgd, V, stats=True)
+    assert n.shape == (0, 4) and st["pixels"] == 0
