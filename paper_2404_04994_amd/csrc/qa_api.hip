@@ -50,8 +50,6 @@ struct Workspace {
     int64_t dr_cap = 0;
     PixRec *pr = nullptr;
     int64_t pr_cap = 0;
-    int32_t *qp_list = nullptr;
-    int64_t qp_cap = 0;
     int32_t *flag_list = nullptr;
     int64_t flag_cap = 0;
     int64_t *counters = nullptr;
@@ -250,7 +248,6 @@ qa_status grow_single(Workspace *w, int64_t P)
     qa_status st;
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
     if ((st = grow(w, w->pr, w->pr_cap, P))) return st;
-    if ((st = grow(w, w->qp_list, w->qp_cap, P))) return st;
     if ((st = grow(w, w->flag_list, w->flag_cap, P))) return st;
     return QA_OK;
 }
@@ -270,10 +267,8 @@ qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, cons
 {
     const bool closed = pb->mode == QA_CLOSED;
     if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
-    QA_HIP(launch_zero_i64(w->counters, C_NUM, s));
-    QA_HIP(launch_prep(w->dr, 1, s));
-    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, s));
-    QA_HIP(launch_qp(w->dr, V, P, w->pr, w->qp_list, w->counters, pb->n_dot, closed, s));
+    QA_HIP(launch_prep(w->dr, 1, w->counters, s));
+    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->counters, pb->n_dot, closed, s));
     if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
     if (nbar) {
         QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
@@ -307,7 +302,7 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
     std::vector<int64_t> key = {pb->n_dot, pb->mode, path, P, (int64_t)(uintptr_t)V,
                                 (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
                                 (int64_t)(uintptr_t)saved, (int64_t)(uintptr_t)w->dr,
-                                (int64_t)(uintptr_t)w->pr, (int64_t)(uintptr_t)w->qp_list,
+                                (int64_t)(uintptr_t)w->pr,
                                 (int64_t)(uintptr_t)w->flag_list};
     auto it = w->graphs.find(key);
     if (it == w->graphs.end()) {
@@ -419,7 +414,7 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
     const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + 4096;
     if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
     if ((st = upload_diag(w, prob))) return st;
-    QA_HIP(launch_prep(w->dr, 1, w->stream));
+    QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream));
     double *accA = w->acc, *accG = accA + kMaxDot * kMaxDot, *accU = accG + kMaxDot * kMaxGate;
     QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, accA, accG,
                            accU, grad_V_dev, prob->n_dot, w->stream));
@@ -673,7 +668,6 @@ void qa_release(void *hip_stream)
     (void)hipStreamSynchronize(w->stream);
     (void)hipFree(w->dr);
     (void)hipFree(w->pr);
-    (void)hipFree(w->qp_list);
     (void)hipFree(w->flag_list);
     (void)hipFree(w->counters);
     (void)hipFree(w->acc);

@@ -306,21 +306,22 @@ __device__ inline void prep_body(DiagRec *dr, double *L, double *Ainv)
 {
     const int n = dr->n;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        // Cholesky C_dd = L L^T (the host has checked positive definiteness)
-        for (int j = 0; j < n; ++j) {
-            double d = dr->Cdd[j * kMaxDot + j];
-            for (int k = 0; k < j; ++k) d -= L[j * kMaxDot + k] * L[j * kMaxDot + k];
-            const double ljj = sqrt(d);
-            L[j * kMaxDot + j] = ljj;
-            for (int i = j + 1; i < n; ++i) {
-                double s = dr->Cdd[i * kMaxDot + j];
-                for (int k = 0; k < j; ++k) s -= L[i * kMaxDot + k] * L[j * kMaxDot + k];
-                L[i * kMaxDot + j] = s / ljj;
-            }
-        }
-    }
+    // Cholesky C_dd = L L^T (the host has checked positive definiteness),
+    // right-looking: thread i keeps row i of the trailing matrix in LDS and
+    // updates it after each pivot column
+    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) L[e] = dr->Cdd[e];
     __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double ljj = sqrt(L[j * kMaxDot + j]);
+        __syncthreads();
+        if (tid >= j && tid < n) L[tid * kMaxDot + j] = (tid == j) ? ljj : L[tid * kMaxDot + j] / ljj;
+        __syncthreads();
+        if (tid > j && tid < n) {
+            const double lij = L[tid * kMaxDot + j];
+            for (int k = j + 1; k <= tid; ++k) L[tid * kMaxDot + k] -= lij * L[k * kMaxDot + j];
+        }
+        __syncthreads();
+    }
     if (tid < n) {
         // column tid of A: L y = e_tid, then L^T a = y
         double y[kMaxDot], a[kMaxDot];

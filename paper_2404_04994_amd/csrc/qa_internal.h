@@ -4,13 +4,14 @@
 //   DiagRec  : per diagram, written by the prologue kernel (k_prep):
 //              C_dd, A = C_dd^{-1} (FP64, symmetric), C_gd, C_dd 1, sums,
 //              and the FP32 / split-BF16 tables the matrix-core scorer reads.
-//   PixRec   : per pixel, written by the setup kernels (k_setup / k_qp):
+//   PixRec   : per pixel, written by the setup kernel (k_setup):
 //              the candidate description (n0, free mask, k) and the FP64
 //              gradient g0 = A (n0 - x_u) and energy U(n0) at the base state.
 //   SavedRec : per pixel, the softargmin state the adjoint needs (the
 //              caller-owned "saved" buffer of qa_soft_charge).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace qa {
@@ -28,7 +29,7 @@ enum Counter {
     C_NEAR_TIE = 4,
     C_GAP_1E9 = 5,
     C_CANDIDATES = 6,
-    C_QP_LIST = 7,      // length of the QP pixel list
+    C_UNUSED7 = 7,
     C_FLAG_LIST = 8,    // length of the full FP64 re-score list
     C_BAND_OVERFLOW = 9,
     C_WORK = 10,        // work-queue cursor of the batched kernel
@@ -94,13 +95,10 @@ struct alignas(8) BatchHdr {
 // error of the launch.
 // -------------------------------------------------------------------------
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s);
-hipError_t launch_prep(DiagRec *dr, int n_diag, hipStream_t s);
+// prologue of n_diag diagrams; also zeroes the C_NUM counters when given
+hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s);
 hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                        int32_t *qp_list, int64_t *counters, int n_dot, bool closed,
-                        hipStream_t s);
-hipError_t launch_qp(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                     const int32_t *qp_list, int64_t *counters, int n_dot, bool closed,
-                     hipStream_t s);
+                        int64_t *counters, int n_dot, bool closed, hipStream_t s);
 // T = 0 argmin in FP64 over the listed pixels (list == nullptr: all P)
 hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P,
                              const int32_t *list, const int64_t *list_count,

@@ -5,12 +5,10 @@
 //   k_prep      per diagram: A = C_dd^{-1} (FP64 Cholesky), C_dd 1, the
 //               pixel-independent energy tables (Sec. 2, Eq. free_energy).
 //   k_setup     per pixel (lane = pixel): x_u = C_gd V, the analytic
-//               continuous minimum (Sec. 3.1.1, App. C/D); pixels where it is
-//               negative go to a list for k_qp; others get their candidate set
-//               (Sec. 3.2) and the base-state gradient.
-//   k_qp        per listed pixel: the constrained minimum of Sec. 3.1.2 in FP64
-//               by a primal-dual active-set iteration whose linear systems are
-//               solved by Cholesky in registers.
+//               continuous minimum (Sec. 3.1.1, App. C/D) and, where it is
+//               negative, the constrained minimum of Sec. 3.1.2 in FP64 by a
+//               primal-dual active-set iteration (Cholesky in registers); then
+//               the candidate set (Sec. 3.2) and the base-state gradient.
 //   k_score_fp64  T = 0 argmin (Eq. argmin) over each pixel's candidate set,
 //               FP64, a group of lanes per pixel walking a Gray code.
 //   k_soft_fwd  kT > 0 softargmin (Sec. 4.2, Eq. softargmin), FP64.
@@ -41,16 +39,18 @@ __global__ void k_zero_f64(double *p, int64_t n)
 // ---------------------------------------------------------------------------
 // K0: per-diagram prologue, one 64-thread block per diagram
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_prep(DiagRec *dr_all)
+__global__ __launch_bounds__(64) void k_prep(DiagRec *dr_all, int64_t *counters)
 {
     __shared__ double L[kMaxDot * kMaxDot];
     __shared__ double Ainv[kMaxDot * kMaxDot];
+    // the call's counters start at zero (no separate memset in the graph)
+    if (counters && blockIdx.x == 0 && threadIdx.x < C_NUM) counters[threadIdx.x] = 0;
     prep_body(dr_all + blockIdx.x, L, Ainv);
 }
 
-hipError_t launch_prep(DiagRec *dr, int n_diag, hipStream_t s)
+hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prep, dim3(n_diag), dim3(64), 0, s, dr);
+    hipLaunchKernelGGL(k_prep, dim3(n_diag), dim3(64), 0, s, dr, counters);
     return hipGetLastError();
 }
 
@@ -89,11 +89,10 @@ template <int NM, bool CLOSED>
 __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
                                                const double *__restrict__ V, int64_t P,
                                                PixRec *__restrict__ pr,
-                                               int32_t *__restrict__ qp_list,
                                                int64_t *__restrict__ counters)
 {
-    __shared__ int64_t sc[3];
-    if (threadIdx.x < 3) sc[threadIdx.x] = 0;
+    __shared__ int64_t sc[4];
+    if (threadIdx.x < 4) sc[threadIdx.x] = 0;
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < P) {
@@ -129,17 +128,17 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
             for (int i = 0; i < NM; ++i) x[i] = 0.0;
             feasible = true;
         }
-        if (feasible) {
-            int dbl = 0;
-            finish_pixel<NM, CLOSED>(dr, x, xu, solved_qp ? 1 : 0, pr + p, &dbl);
-            if (dbl) atomicAdd((unsigned long long *)&sc[2], 1ull);
-            if (solved_qp) atomicAdd((unsigned long long *)&sc[1], 1ull);
-        } else {
-            const unsigned long long slot =
-                atomicAdd((unsigned long long *)&counters[C_QP_LIST], 1ull);
-            qp_list[slot] = (int32_t)p;
-            atomicAdd((unsigned long long *)&sc[1], 1ull);
+        int flags = solved_qp ? 1 : 0;
+        if (!feasible) {
+            // the QP of Sec. 3.1.2, solved exactly in this lane
+            const bool ok = qp_solve<NM, CLOSED>(dr, xu, x);
+            flags = ok ? 1 : 3;
         }
+        int dbl = 0;
+        finish_pixel<NM, CLOSED>(dr, x, xu, flags, pr + p, &dbl);
+        if (dbl) atomicAdd((unsigned long long *)&sc[2], 1ull);
+        if (flags & 1) atomicAdd((unsigned long long *)&sc[1], 1ull);
+        if (flags & 2) atomicAdd((unsigned long long *)&sc[3], 1ull);
         atomicAdd((unsigned long long *)&sc[0], 1ull);
     }
     __syncthreads();
@@ -147,38 +146,8 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
         block_add_counter(counters, C_PIXELS, sc[0]);
         block_add_counter(counters, C_QP, sc[1]);
         block_add_counter(counters, C_DOUBLED, sc[2]);
+        block_add_counter(counters, C_QP_FAIL, sc[3]);
     }
-}
-
-template <int NM, bool CLOSED>
-__global__ __launch_bounds__(64) void k_qp(const DiagRec *__restrict__ dr,
-                                           const double *__restrict__ V, int64_t P,
-                                           PixRec *__restrict__ pr,
-                                           const int32_t *__restrict__ qp_list,
-                                           int64_t *__restrict__ counters)
-{
-    const int64_t count = counters[C_QP_LIST];
-    const int n = dr->n, g = dr->g;
-    int64_t fails = 0, dbls = 0;
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < count;
-         it += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = qp_list[it];
-        double xu[NM], x[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            double s = 0.0;
-            if (i < n)
-                for (int j = 0; j < g; ++j) s += dr->Cgd[i * kMaxGate + j] * V[p * g + j];
-            xu[i] = s;
-        }
-        const bool converged = qp_solve<NM, CLOSED>(dr, xu, x);
-        int dbl = 0;
-        finish_pixel<NM, CLOSED>(dr, x, xu, 1 | (converged ? 0 : 2), pr + p, &dbl);
-        fails += converged ? 0 : 1;
-        dbls += dbl;
-    }
-    if (fails) atomicAdd((unsigned long long *)&counters[C_QP_FAIL], (unsigned long long)fails);
-    if (dbls) atomicAdd((unsigned long long *)&counters[C_DOUBLED], (unsigned long long)dbls);
 }
 
 #define QA_DISPATCH_NM(n, CALL)                        \
@@ -190,34 +159,15 @@ __global__ __launch_bounds__(64) void k_qp(const DiagRec *__restrict__ dr,
     } while (0)
 
 hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                        int32_t *qp_list, int64_t *counters, int n_dot, bool closed,
-                        hipStream_t s)
+                        int64_t *counters, int n_dot, bool closed, hipStream_t s)
 {
     const dim3 grid((unsigned)((P + 255) / 256)), block(256);
     if (closed)
         QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>), grid, block, 0, s, dr, V, P,
-                                                 pr, qp_list, counters));
+                                                 pr, counters));
     else
         QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, false>), grid, block, 0, s, dr, V,
-                                                 P, pr, qp_list, counters));
-    return hipGetLastError();
-}
-
-hipError_t launch_qp(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                     const int32_t *qp_list, int64_t *counters, int n_dot, bool closed,
-                     hipStream_t s)
-{
-    // grid-stride over the list, whose length is only known on the device
-    int64_t blocks = (P + 63) / 64;
-    if (blocks > 4096) blocks = 4096;
-    if (blocks < 1) blocks = 1;
-    const dim3 grid((unsigned)blocks), block(64);
-    if (closed)
-        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_qp<NM_, true>), grid, block, 0, s, dr, V, P, pr,
-                                                 qp_list, counters));
-    else
-        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_qp<NM_, false>), grid, block, 0, s, dr, V, P, pr,
-                                                 qp_list, counters));
+                                                 P, pr, counters));
     return hipGetLastError();
 }
 
@@ -323,9 +273,12 @@ hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P,
                              const int32_t *list, const int64_t *list_count, int32_t *n_out,
                              int64_t *counters, int n_dot, hipStream_t s)
 {
+    // list mode re-scores the few near-tie pixels whose band overflowed: a
+    // small grid strides over the list (its length is only known on device)
     QA_DISPATCH_GROUP(n_dot, hipLaunchKernelGGL((k_score_fp64<LG_, NM_>),
-                                                dim3(group_blocks(P, LG_, 8192)), dim3(256), 0, s,
-                                                dr, pr, P, list, list_count, n_out, counters));
+                                                dim3(group_blocks(P, LG_, list ? 64 : 8192)),
+                                                dim3(256), 0, s, dr, pr, P, list, list_count, n_out,
+                                                counters));
     return hipGetLastError();
 }
 
