@@ -130,6 +130,21 @@ typedef struct {
 qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P,
                           int32_t *n_out_dev, qa_stats *stats, void *hip_stream);
 
+/* Constrained continuous minimum of every pixel (Sec. 3.1): x* = the
+ * analytic minimum (Sec. 3.1.1; App. C for open, App. D for closed arrays)
+ * when it is non-negative, otherwise the exact solution of the QP of
+ * Sec. 3.1.2 (x >= 0, and sum x = N_hat for closed arrays) in FP64.
+ *   x_out_dev     : device, P x N FP64, receives x*.
+ *   flags_out_dev : device, P int32, or NULL; bit0 = the QP was solved,
+ *                   bit1 = the QP iteration did not settle (x* is then its
+ *                   last iterate), bit2 = the threshold doubled when the
+ *                   candidate set was formed (closed, t < 1).
+ * This is the first stage of qa_ground_state and qa_soft_charge, exposed so
+ * that the continuous minimum can be checked and reused on its own. */
+qa_status qa_continuous_min(const qa_problem *prob, const double *V_dev, int64_t P,
+                            double *x_out_dev, int32_t *flags_out_dev, qa_stats *stats,
+                            void *hip_stream);
+
 /* Thermal softargmin (Sec. 4.2, Eq. softargmin) over the candidate set of
  * each pixel, in FP64.
  *   nbar_out_dev : device, P x N FP64, receives <n> per pixel.

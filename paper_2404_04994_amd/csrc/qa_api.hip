@@ -369,6 +369,29 @@ qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P
     return read_stats(w, stats);
 }
 
+qa_status qa_continuous_min(const qa_problem *prob, const double *V_dev, int64_t P,
+                            double *x_out_dev, int32_t *flags_out_dev, qa_stats *stats,
+                            void *hip_stream)
+{
+    g_err.clear();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
+    if (P == 0) {
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return QA_OK;
+    }
+    if (!V_dev || !x_out_dev) return fail(QA_E_NULL, "V_dev or x_out_dev is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    if ((st = grow_single(w, P))) return st;
+    if ((st = upload_diag(w, prob))) return st;
+    QA_HIP(launch_prep(w->dr, 1, w->counters, w->stream));
+    QA_HIP(launch_setup(w->dr, V_dev, P, w->pr, w->counters, prob->n_dot,
+                        prob->mode == QA_CLOSED, w->stream, x_out_dev, flags_out_dev));
+    return read_stats(w, stats);
+}
+
 size_t qa_saved_bytes(int64_t P, int32_t n_dot)
 {
     (void)n_dot;

@@ -103,7 +103,7 @@ __device__ __forceinline__ double base_state(const double *__restrict__ A, int n
 
 // Cholesky solve of an SPD system held as a packed lower triangle, M fixed.
 template <int M>
-__device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2], double (&b)[M])
+__host__ __device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2], double (&b)[M])
 {
 #define LIDX(i, j) ((i) * ((i) + 1) / 2 + (j))
 #pragma unroll
@@ -151,7 +151,7 @@ __device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2], double 
 // grows (Chandrasekaran's method), at most N rounds.  Returns false when the
 // iteration did not settle (x is then the last iterate, clipped at 0).
 template <int NM, bool CLOSED>
-__device__ bool qp_solve(const DiagRec *__restrict__ dr, const double (&xu)[NM], double (&x)[NM])
+__host__ __device__ bool qp_solve(const DiagRec *__restrict__ dr, const double (&xu)[NM], double (&x)[NM])
 {
     constexpr int M = NM + (CLOSED ? 1 : 0);
     const int n = dr->n;

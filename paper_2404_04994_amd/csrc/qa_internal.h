@@ -97,8 +97,10 @@ struct alignas(8) BatchHdr {
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s);
 // prologue of n_diag diagrams; also zeroes the C_NUM counters when given
 hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s);
+// setup of every pixel; x_out (P x N) / flags_out (P) optional copies of x*
 hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                        int64_t *counters, int n_dot, bool closed, hipStream_t s);
+                        int64_t *counters, int n_dot, bool closed, hipStream_t s,
+                        double *x_out = nullptr, int32_t *flags_out = nullptr);
 // T = 0 argmin in FP64 over the listed pixels (list == nullptr: all P)
 hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P,
                              const int32_t *list, const int64_t *list_count,

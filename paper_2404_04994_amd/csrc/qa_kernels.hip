@@ -89,7 +89,9 @@ template <int NM, bool CLOSED>
 __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
                                                const double *__restrict__ V, int64_t P,
                                                PixRec *__restrict__ pr,
-                                               int64_t *__restrict__ counters)
+                                               int64_t *__restrict__ counters,
+                                               double *__restrict__ x_out,
+                                               int32_t *__restrict__ flags_out)
 {
     __shared__ int64_t sc[4];
     if (threadIdx.x < 4) sc[threadIdx.x] = 0;
@@ -136,6 +138,12 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
         }
         int dbl = 0;
         finish_pixel<NM, CLOSED>(dr, x, xu, flags, pr + p, &dbl);
+        if (x_out) {
+#pragma unroll
+            for (int i = 0; i < NM; ++i)
+                if (i < n) x_out[p * n + i] = x[i];
+        }
+        if (flags_out) flags_out[p] = flags | (dbl ? 4 : 0);
         if (dbl) atomicAdd((unsigned long long *)&sc[2], 1ull);
         if (flags & 1) atomicAdd((unsigned long long *)&sc[1], 1ull);
         if (flags & 2) atomicAdd((unsigned long long *)&sc[3], 1ull);
@@ -159,15 +167,16 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
     } while (0)
 
 hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                        int64_t *counters, int n_dot, bool closed, hipStream_t s)
+                        int64_t *counters, int n_dot, bool closed, hipStream_t s,
+                        double *x_out, int32_t *flags_out)
 {
     const dim3 grid((unsigned)((P + 255) / 256)), block(256);
     if (closed)
         QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>), grid, block, 0, s, dr, V, P,
-                                                 pr, counters));
+                                                 pr, counters, x_out, flags_out));
     else
         QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, false>), grid, block, 0, s, dr, V,
-                                                 P, pr, counters));
+                                                 P, pr, counters, x_out, flags_out));
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ QA_OPEN, QA_CLOSED = 0, 1
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
 STATUS = {0: "QA_OK", 1: "QA_E_NULL", 2: "QA_E_SHAPE", 3: "QA_E_NOT_SYMMETRIC", 4: "QA_E_NOT_PD",
           5: "QA_E_RANGE", 6: "QA_E_UNSUPPORTED", 7: "QA_E_WORKSPACE", 8: "QA_E_DEVICE"}
-EXPORTS = ("qa_ground_state", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
+EXPORTS = ("qa_ground_state", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
            "qa_ground_state_batched", "qa_last_error", "qa_release", "qa_version",
            "qa_timing_enable", "qa_timing_reset", "qa_timing_sum", "qa_graphs_enable")
 
@@ -62,6 +62,7 @@ def load():
         i64p = C.POINTER(C.c_int64)
         lib.qa_ground_state.argtypes = [pb, vp, C.c_int64, vp, st, vp]
         lib.qa_soft_charge.argtypes = [pb, vp, C.c_int64, vp, vp, st, vp]
+        lib.qa_continuous_min.argtypes = [pb, vp, C.c_int64, vp, vp, st, vp]
         lib.qa_soft_charge_backward.argtypes = [pb, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
         lib.qa_ground_state_batched.argtypes = [pb, C.c_int32, vp, i64p, i64p, i64p, vp, vp, st, vp]
         lib.qa_saved_bytes.argtypes = [C.c_int64, C.c_int32]
@@ -74,7 +75,7 @@ def load():
         lib.qa_timing_reset.argtypes = [vp]
         lib.qa_timing_sum.argtypes = [vp, C.POINTER(C.c_double), i64p]
         lib.qa_timing_sum.restype = C.c_int
-        for f in ("qa_ground_state", "qa_soft_charge", "qa_soft_charge_backward",
+        for f in ("qa_ground_state", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward",
                   "qa_ground_state_batched"):
             getattr(lib, f).restype = C.c_int
         _lib = lib
@@ -135,6 +136,22 @@ def ground_state(cdd, cgd, V, closed=False, nhat=0, t=1.0, precision="fp64", str
                                _stream(stream)))
     del keep
     return (out, st.as_dict()) if stats else out
+
+
+def continuous_min(cdd, cgd, V, closed=False, nhat=0, stream=None, stats=False):
+    """x* of every pixel (Sec. 3.1): (x FP64 (P, N), flags int32 (P,)[, stats])."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, 0.0, 1.0, "fp64")
+    V = _device_V(V, pb.n_gate)
+    P = V.shape[0]
+    x = torch.empty((P, pb.n_dot), dtype=torch.float64, device=V.device)
+    fl = torch.empty(max(P, 1), dtype=torch.int32, device=V.device)
+    st = Stats() if stats else None
+    _check(lib.qa_continuous_min(C.byref(pb), C.c_void_p(V.data_ptr()), P, C.c_void_p(x.data_ptr()),
+                                 C.c_void_p(fl.data_ptr()), C.byref(st) if st else None,
+                                 _stream(stream)))
+    del keep
+    return (x, fl[:P], st.as_dict()) if stats else (x, fl[:P])
 
 
 def saved_bytes(P: int, n_dot: int) -> int:
