@@ -50,10 +50,12 @@ def compare(qa, oracle, d, prec, idx=None):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_grid16_small_full_parity(qa, oracle, prec):
-    """4x4 array on a 40 x 40 sweep: every pixel against the oracle."""
+    """4x4 array on a 40 x 40 sweep: every pixel against the oracle.  The
+    share of pixels the band sends to the FP64 re-score is bounded: the
+    BF16x2 band (2^-15 S) is four times wider than the FP32 / BF16x3 one."""
     d = W.grid4x4(201, npix=40)
     _, st = compare(qa, oracle, d, prec)
-    assert st["near_tie_pixels"] <= 0.05 * d.P
+    assert st["near_tie_pixels"] <= (0.12 if prec == "bf16x2" else 0.05) * d.P
 
 
 @pytest.mark.parametrize("prec", PRECS)
