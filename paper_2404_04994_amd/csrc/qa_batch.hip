@@ -18,12 +18,12 @@
 
 namespace qa {
 
-__global__ __launch_bounds__(64) void k_prep_batch(const BatchHdr *__restrict__ hdr,
+__global__ __launch_bounds__(kPrepThreads) void k_prep_batch(const BatchHdr *__restrict__ hdr,
                                                    const double *__restrict__ mats,
                                                    DiagRec *__restrict__ recs)
 {
-    __shared__ double L[kMaxDot * kMaxDot];
-    __shared__ double Ainv[kMaxDot * kMaxDot];
+    __shared__ double M[kMaxDot * kMaxDot];
+    __shared__ double red[8];
     const BatchHdr h = hdr[blockIdx.x];
     DiagRec *dr = recs + blockIdx.x;
     const int n = h.n, g = h.g;
@@ -47,13 +47,13 @@ __global__ __launch_bounds__(64) void k_prep_batch(const BatchHdr *__restrict__ 
         dr->prec = 0;
     }
     __syncthreads();
-    prep_body(dr, L, Ainv);
+    prep_body(dr, M, red);
 }
 
 hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *recs, int n_diag,
                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prep_batch, dim3(n_diag), dim3(64), 0, s, hdr, mats, recs);
+    hipLaunchKernelGGL(k_prep_batch, dim3(n_diag), dim3(kPrepThreads), 0, s, hdr, mats, recs);
     return hipGetLastError();
 }
 

@@ -299,104 +299,102 @@ __device__ __forceinline__ double group_sum(double v)
 // ---------------------------------------------------------------------------
 // K0: per-diagram prologue
 // ---------------------------------------------------------------------------
-// Prologue of one diagram, run by one 64-thread block: A = C_dd^{-1} by
-// Cholesky (FP64), C_dd 1, 1^T C_dd 1, sum|A|/2 and, for n >= 9, the tables of
-// the matrix-core scorer.  L and Ainv are kMaxDot^2 doubles of LDS.
-__device__ inline void prep_body(DiagRec *dr, double *L, double *Ainv)
+constexpr int kPrepThreads = 256;  // one thread per element of a 16 x 16 matrix
+
+// Prologue of one diagram, run by one 256-thread block (thread t owns element
+// (t / 16, t % 16)): A = C_dd^{-1} (FP64), C_dd 1, 1^T C_dd 1, sum|A|/2 and the
+// pixel-independent energy tables.  M is 256 doubles of LDS, red 8 doubles.
+//
+// The inverse is an in-place Gauss-Jordan elimination of the positive
+// definite C_dd without pivoting (every pivot is a diagonal entry of a
+// Schur complement of a positive definite matrix, hence positive; the host
+// has checked definiteness by Cholesky).  Pivot k maps
+//   m_kk -> 1/p,  m_kj -> m_kj/p,  m_ik -> -m_ik/p,  m_ij -> m_ij - m_ik m_kj/p,
+// and after the n pivots M = C_dd^{-1}.  Dots beyond n stay identity rows.
+__device__ inline void prep_body(DiagRec *dr, double *M, double *red)
 {
     const int n = dr->n;
     const int tid = threadIdx.x;
-    // Cholesky C_dd = L L^T (the host has checked positive definiteness),
-    // right-looking: thread i keeps row i of the trailing matrix in LDS and
-    // updates it after each pivot column
-    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) L[e] = dr->Cdd[e];
+    const int i = tid >> 4, j = tid & 15;
+    const double cij = dr->Cdd[tid];
+    double m = (i < n && j < n) ? cij : (i == j ? 1.0 : 0.0);
+    M[tid] = m;
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double ljj = sqrt(L[j * kMaxDot + j]);
+    for (int k = 0; k < n; ++k) {
+        const double piv = M[k * kMaxDot + k];
+        const double mik = M[i * kMaxDot + k], mkj = M[k * kMaxDot + j];
         __syncthreads();
-        if (tid >= j && tid < n) L[tid * kMaxDot + j] = (tid == j) ? ljj : L[tid * kMaxDot + j] / ljj;
-        __syncthreads();
-        if (tid > j && tid < n) {
-            const double lij = L[tid * kMaxDot + j];
-            for (int k = j + 1; k <= tid; ++k) L[tid * kMaxDot + k] -= lij * L[k * kMaxDot + j];
-        }
+        const double r = 1.0 / piv;
+        if (i == k && j == k) m = r;
+        else if (i == k) m = mkj * r;
+        else if (j == k) m = -mik * r;
+        else m = m - mik * mkj * r;
+        M[tid] = m;
         __syncthreads();
     }
-    if (tid < n) {
-        // column tid of A: L y = e_tid, then L^T a = y
-        double y[kMaxDot], a[kMaxDot];
-        for (int i = 0; i < n; ++i) {
-            double s = (i == tid) ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) s -= L[i * kMaxDot + k] * y[k];
-            y[i] = s / L[i * kMaxDot + i];
-        }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = y[i];
-            for (int k = i + 1; k < n; ++k) s -= L[k * kMaxDot + i] * a[k];
-            a[i] = s / L[i * kMaxDot + i];
-        }
-        for (int i = 0; i < n; ++i) Ainv[i * kMaxDot + tid] = a[i];
-    }
+    // exactly symmetric A (the energy tables and every kernel read this copy)
+    const double a = (i < n && j < n) ? 0.5 * (m + M[j * kMaxDot + i]) : 0.0;
     __syncthreads();
-    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) {
-        const int i = e / kMaxDot, j = e % kMaxDot;
-        double v = 0.0;
-        if (i < n && j < n) v = 0.5 * (Ainv[i * kMaxDot + j] + Ainv[j * kMaxDot + i]);
-        dr->A[e] = v;
-        Ainv[e] = v;  // exactly symmetric copy for the tables below
-    }
-    __syncthreads();
+    M[tid] = a;
+    dr->A[tid] = a;
+    // sum |A_ij| / 2: wave sums, then the four partial sums
+    double sa = fabs(a);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sa += __shfl_xor(sa, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = sa;
+    // C_dd 1 and 1^T C_dd 1 (row sums of the input, 16 lanes of wave 0)
     if (tid < kMaxDot) {
-        double s = 0.0;
+        double c = 0.0;
         if (tid < n)
-            for (int j = 0; j < n; ++j) s += dr->Cdd[tid * kMaxDot + j];
-        dr->c[tid] = s;
+            for (int q = 0; q < n; ++q) c += dr->Cdd[tid * kMaxDot + q];
+        dr->c[tid] = c;
+        double oc = c;
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) oc += __shfl_xor(oc, off, 16);
+        if (tid == 0) red[4] = oc;
     }
+    __syncthreads();
     if (tid == 0) {
-        double s = 0.0, sa = 0.0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                s += dr->Cdd[i * kMaxDot + j];
-                sa += fabs(Ainv[i * kMaxDot + j]);
-            }
-        dr->one_c = s;
-        dr->sumabs = (float)(0.5 * sa);
+        dr->one_c = red[4];
+        dr->sumabs = (float)(0.5 * (red[0] + red[1] + red[2] + red[3]));
     }
     // tables of the matrix-core scorer: low part = dots 0..7, high = 8..n-1
     if (n >= 9) {
         const int nh = n - 8;
-        for (int e = tid; e < 16 * 8; e += blockDim.x) {
-            const int r = e / 8, i = e % 8;
+        if (tid < 16 * 8) {
+            const int r = tid >> 3, q = tid & 7;
             double t1 = 0.0, t2 = 0.0;
-            for (int j = 0; j < 4; ++j) {
-                if ((r >> j & 1) && j < nh) t1 += Ainv[i * kMaxDot + 8 + j];
-                if ((r >> j & 1) && j + 4 < nh) t2 += Ainv[i * kMaxDot + 12 + j];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if ((r >> b & 1) && b < nh) t1 += M[q * kMaxDot + 8 + b];
+                if ((r >> b & 1) && b + 4 < nh) t2 += M[q * kMaxDot + 12 + b];
             }
-            dr->T1[r][i] = (float)t1;
-            dr->T2[r][i] = (float)t2;
+            dr->T1[r][q] = (float)t1;
+            dr->T2[r][q] = (float)t2;
         }
-        for (int e = tid; e < 256; e += blockDim.x) {
-            double hh = 0.0, hl = 0.0;
-            for (int a = 0; a < 8; ++a)
-                for (int b = 0; b < 8; ++b) {
-                    if ((e >> a & 1) && (e >> b & 1)) {
-                        hl += Ainv[a * kMaxDot + b];
-                        if (a < nh && b < nh) hh += Ainv[(8 + a) * kMaxDot + 8 + b];
-                    }
+        double hh = 0.0, hl = 0.0;
+#pragma unroll
+        for (int x = 0; x < 8; ++x)
+#pragma unroll
+            for (int y = 0; y < 8; ++y) {
+                if ((tid >> x & 1) && (tid >> y & 1)) {
+                    hl += M[x * kMaxDot + y];
+                    if (x < nh && y < nh) hh += M[(8 + x) * kMaxDot + 8 + y];
                 }
-            dr->hlo[e] = (float)(0.5 * hl);
-            dr->Hhi[e] = (e < (1 << nh)) ? (float)(0.5 * hh) : 1e30f;
-        }
+            }
+        dr->hlo[tid] = (float)(0.5 * hl);
+        dr->Hhi[tid] = (tid < (1 << nh)) ? (float)(0.5 * hh) : 1e30f;
     } else {
         // whole-box table of the lane walk: h(s) = 1/2 s^T A s, s < 2^n
-        for (int e = tid; e < 256; e += blockDim.x) {
-            double h = 0.0;
-            if (e < (1 << n))
-                for (int a = 0; a < n; ++a)
-                    for (int b = 0; b < n; ++b)
-                        if ((e >> a & 1) && (e >> b & 1)) h += Ainv[a * kMaxDot + b];
-            dr->hs[e] = 0.5 * h;
+        double h = 0.0;
+        if (tid < (1 << n)) {
+#pragma unroll
+            for (int x = 0; x < 8; ++x)
+#pragma unroll
+                for (int y = 0; y < 8; ++y)
+                    if ((tid >> x & 1) && (tid >> y & 1)) h += M[x * kMaxDot + y];
         }
+        dr->hs[tid] = 0.5 * h;
     }
 }
 

@@ -2,13 +2,13 @@
 // path (van Straaten et al., arXiv 2404.04994), except the matrix-core
 // scorer (qa_mfma.hip).
 //
-//   k_prep      per diagram: A = C_dd^{-1} (FP64 Cholesky), C_dd 1, the
+//   k_prep      per diagram: A = C_dd^{-1} (FP64 Gauss-Jordan), C_dd 1, the
 //               pixel-independent energy tables (Sec. 2, Eq. free_energy).
-//   k_setup     per pixel (lane = pixel): x_u = C_gd V, the analytic
-//               continuous minimum (Sec. 3.1.1, App. C/D) and, where it is
-//               negative, the constrained minimum of Sec. 3.1.2 in FP64 by a
-//               primal-dual active-set iteration (Cholesky in registers); then
-//               the candidate set (Sec. 3.2) and the base-state gradient.
+//   k_setup     per pixel (a group of lanes, lane = dot): x_u = C_gd V, the
+//               analytic continuous minimum (Sec. 3.1.1, App. C/D) and, where
+//               it is negative, the constrained minimum of Sec. 3.1.2 in FP64
+//               by an active-set elimination across the group; then the
+//               candidate set (Sec. 3.2) and the base-state gradient.
 //   k_score_fp64  T = 0 argmin (Eq. argmin) over each pixel's candidate set,
 //               FP64, a group of lanes per pixel walking a Gray code.
 //   k_soft_fwd  kT > 0 softargmin (Sec. 4.2, Eq. softargmin), FP64.
@@ -37,52 +37,104 @@ __global__ void k_zero_f64(double *p, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
-// K0: per-diagram prologue, one 64-thread block per diagram
+// K0: per-diagram prologue, one 256-thread block per diagram
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_prep(DiagRec *dr_all, int64_t *counters)
+__global__ __launch_bounds__(kPrepThreads) void k_prep(DiagRec *dr_all, int64_t *counters)
 {
-    __shared__ double L[kMaxDot * kMaxDot];
-    __shared__ double Ainv[kMaxDot * kMaxDot];
+    __shared__ double M[kMaxDot * kMaxDot];
+    __shared__ double red[8];
     // the call's counters start at zero (no separate memset in the graph)
     if (counters && blockIdx.x == 0 && threadIdx.x < C_NUM) counters[threadIdx.x] = 0;
-    prep_body(dr_all + blockIdx.x, L, Ainv);
+    prep_body(dr_all + blockIdx.x, M, red);
 }
 
 hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prep, dim3(n_diag), dim3(64), 0, s, dr, counters);
+    hipLaunchKernelGGL(k_prep, dim3(n_diag), dim3(kPrepThreads), 0, s, dr, counters);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// K1: candidate set and base-state gradient of one pixel
+// K1: continuous minimum, candidate set and base-state gradient.
+//
+// A group of NM lanes per pixel, lane i = dot i (NM = 16: four pixels per
+// wave).  Every branch is uniform within a group and the shuffles read lanes
+// of the same group only.  The matrices sit in LDS transposed, so that the
+// lanes of a group read consecutive addresses.
+//
+// The QP of Sec. 3.1.2 (where the analytic minimum is negative) is solved in
+// its KKT form: for the active set W (x_W = 0) the multipliers solve
+// K_WW mu_W = -x0_W and the free dots follow as x = x0 + K_{.W} mu_W, with
+// x0 the analytic minimum and K = C_dd (open) or C_dd - c c^T / 1^T c with
+// c = C_dd 1 (closed: the equality multiplier eliminated).  The system is
+// Gauss-Jordan eliminated on [K | x0], one pivot per dot of W (rows held by
+// their lanes, the pivot row broadcast by shuffles): afterwards the column
+// holds -mu_i on W and x_i off W.  The active set follows the primal-dual
+// update (Hintermueller, Ito and Kunisch, SIAM J. Optim. 13, 2003): keep dots
+// with mu > -tol, add dots with x < -tol, stop when W repeats.  Added dots are
+// pivoted on the current elimination; a dot leaving W restarts it.  For open
+// arrays C_dd is an M-matrix and W only grows (Chandrasekaran's method), so
+// at most N pivots are taken.  Every non-pivot K_WW is a principal submatrix
+// of a positive definite matrix (closed: on any proper subset of the dots),
+// so no pivoting is needed.
 // ---------------------------------------------------------------------------
-template <int NM, bool CLOSED>
-__device__ void finish_pixel(const DiagRec *__restrict__ dr, const double (&x)[NM],
-                             const double (&xu)[NM], int flags, PixRec *__restrict__ out,
-                             int *doubled)
+template <int NM>
+__device__ __forceinline__ uint32_t group_ballot(bool pred)
 {
-    int n0[NM];
-    uint32_t fm;
-    int k;
-    flags |= candidate_set<NM>(dr, CLOSED, x, n0, fm, k);
-    *doubled = (flags & 4) ? 1 : 0;
-    double g0[NM];
-    const double u0 = base_state<NM>(dr->A, dr->n, n0, xu, g0);
+    const unsigned long long b = __ballot(pred);
+    const int sh = (threadIdx.x & (kWave - 1)) & ~(NM - 1);
+    return (uint32_t)((b >> sh) & ((1ull << NM) - 1ull));
+}
+
+template <int NM>
+__device__ __forceinline__ int group_isum(int v)
+{
 #pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        out->g0[i] = g0[i];
-        out->n0[i] = (int16_t)n0[i];
-    }
+    for (int off = NM / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, NM);
+    return v;
+}
+
+template <int NM>
+__device__ __forceinline__ double group_dsum(double v)
+{
 #pragma unroll
-    for (int i = NM; i < kMaxDot; ++i) {
-        out->g0[i] = 0.0;
-        out->n0[i] = 0;
+    for (int off = NM / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, NM);
+    return v;
+}
+
+template <int NM>
+__device__ __forceinline__ double group_dmax(double v)
+{
+#pragma unroll
+    for (int off = NM / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, NM));
+    return v;
+}
+
+// One Gauss-Jordan pivot on dot k of [K | x]: lane `dot` holds row `dot` in
+// r[] and its right-hand side in v; `base` is the group's first lane.
+template <int NM>
+__device__ __forceinline__ void gj_pivot(double (&r)[NM], double &v, int k, int dot, int base)
+{
+    const int src = base + k;
+    double rik = r[0];
+#pragma unroll
+    for (int q = 1; q < NM; ++q) rik = (k == q) ? r[q] : rik;
+    const double piv = __shfl(rik, src, kWave);
+    double pr[NM];
+#pragma unroll
+    for (int q = 0; q < NM; ++q) pr[q] = __shfl(r[q], src, kWave);
+    const double pv = __shfl(v, src, kWave);
+    const double rp = 1.0 / piv;
+    if (dot == k) {
+#pragma unroll
+        for (int q = 0; q < NM; ++q) r[q] = pr[q] * rp;
+        v = pv * rp;
+    } else {
+        const double f = rik * rp;
+#pragma unroll
+        for (int q = 0; q < NM; ++q) r[q] -= f * pr[q];
+        v -= f * pv;
     }
-    out->u0 = u0;
-    out->free = fm;
-    out->k = k;
-    out->flags = flags;
 }
 
 template <int NM, bool CLOSED>
@@ -93,68 +145,141 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
                                                double *__restrict__ x_out,
                                                int32_t *__restrict__ flags_out)
 {
-    __shared__ int64_t sc[4];
-    if (threadIdx.x < 4) sc[threadIdx.x] = 0;
+    __shared__ double sK[NM * NM];         // K (symmetric), identity beyond n
+    __shared__ double sA[NM * NM];         // A (symmetric)
+    __shared__ double sG[kMaxGate * NM];   // C_gd transposed: sG[j * NM + i]
+    __shared__ double sc[NM];              // C_dd 1
+    __shared__ unsigned long long cnt[4];
+    const int n = dr->n, g = dr->g;
+    const double one_c = dr->one_c;
+    for (int e = threadIdx.x; e < NM * NM; e += blockDim.x) {
+        const int i = e / NM, j = e % NM;
+        double kv = (i == j) ? 1.0 : 0.0;
+        if (i < n && j < n) {
+            kv = dr->Cdd[i * kMaxDot + j];
+            if (CLOSED) kv -= dr->c[i] * dr->c[j] / one_c;
+        }
+        sK[e] = kv;
+        sA[e] = dr->A[i * kMaxDot + j];
+    }
+    for (int e = threadIdx.x; e < kMaxGate * NM; e += blockDim.x) {
+        const int j = e / NM, i = e % NM;
+        sG[e] = dr->Cgd[i * kMaxGate + j];
+    }
+    if (threadIdx.x < NM) sc[threadIdx.x] = dr->c[threadIdx.x];
+    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+
+    const int dot = threadIdx.x & (NM - 1);
+    const int base = (threadIdx.x & (kWave - 1)) & ~(NM - 1);
+    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / NM) + threadIdx.x / NM;
+    const int64_t pc = p < P ? p : P - 1;  // groups past the end repeat the last pixel
+    const bool is_dot = dot < n;
+
+    // x_u = C_gd V
+    double xu = 0.0;
+    for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * V[pc * g + j];
+    if (!is_dot) xu = 0.0;
+    // analytic minimum: open x = x_u; closed adds (N_hat - 1^T x_u) C_dd 1 / (1^T C_dd 1)
+    double x0 = xu;
+    if (CLOSED) {
+        const double lam = ((double)dr->nhat - group_dsum<NM>(xu)) / one_c;
+        x0 = is_dot ? xu + lam * sc[dot] : 0.0;
+    }
+    double x = x0;
+    int flags = 0;
+    uint32_t W = group_ballot<NM>(is_dot && x0 < 0.0);
+    if (CLOSED && dr->nhat == 0) {
+        // x = 0 is the only admissible point of a closed empty array
+        flags = W ? 1 : 0;
+        x = 0.0;
+        W = 0;
+    }
+    if (W) {
+        const double tol = 1e-13 * group_dmax<NM>(fmax(1.0, fabs(xu)));
+        double r[NM], v = x0;
+        uint32_t done = 0;
+        bool settled = false;
+        for (int round = 0; round < 4 * NM + 4; ++round) {
+            if (done == 0) {
+#pragma unroll
+                for (int q = 0; q < NM; ++q) r[q] = sK[q * NM + dot];
+                v = x0;
+            }
+            for (uint32_t todo = W & ~done; todo; todo &= todo - 1)
+                gj_pivot<NM>(r, v, __ffs(todo) - 1, dot, base);
+            done = W;
+            const bool in_w = W >> dot & 1u;
+            x = in_w ? 0.0 : v;
+            const bool keep = is_dot && (in_w ? (-v > -tol) : (v < -tol));
+            const uint32_t Wn = group_ballot<NM>(keep);
+            if (Wn == W) { settled = true; break; }
+            if (W & ~Wn) done = 0;  // a dot leaves the active set: eliminate afresh
+            W = Wn;
+        }
+        x = is_dot ? fmax(x, 0.0) : 0.0;
+        flags = settled ? 1 : 3;
+    }
+
+    // candidate set (Sec. 3.2): base n0, free dots, closed: k raised free dots
+    double t = dr->t;
+    int n0 = 0, k = -1, cflags = 0;
+    bool freed = false;
+    for (int iter = 0; iter < 80; ++iter) {
+        // the box starts at floor(x* + 1e-9): a continuous minimum on an
+        // integer keeps that integer as its floor whatever its last bit
+        const double f = floor(x + 1e-9);
+        const double fr = x - f;
+        freed = is_dot && ((t >= 1.0) || (fabs(fr - 0.5) <= 0.5 * t));
+        n0 = is_dot ? (int)f + ((!freed && fr > 0.5) ? 1 : 0) : 0;
+        if (!CLOSED) break;
+        const int sum0 = group_isum<NM>(n0);
+        const int nfree = __popc(group_ballot<NM>(freed));
+        const int need = dr->nhat - sum0;
+        if (need >= 0 && need <= nfree) { k = need; break; }
+        if (t >= 1.0) {  // |sum x* - N_hat| < 1 makes this unreachable
+            k = need < 0 ? 0 : nfree;
+            cflags |= 2;
+            break;
+        }
+        t = (t > 0.0) ? fmin(1.0, 2.0 * t) : 1.0;
+        cflags |= 4;
+    }
+    const uint32_t fm = group_ballot<NM>(freed);
+
+    // g0 = A (n0 - x_u) and U(n0) = 1/2 (n0 - x_u)^T g0 (Eq. free_energy)
+    const double z = is_dot ? (double)n0 - xu : 0.0;
+    double g0 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NM; ++q) g0 += sA[q * NM + dot] * __shfl(z, base + q, kWave);
+    const double u0 = 0.5 * group_dsum<NM>(z * g0);
+
     if (p < P) {
-        const int n = dr->n, g = dr->g;
-        double xu[NM], x[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            double s = 0.0;
-            if (i < n)
-                for (int j = 0; j < g; ++j) s += dr->Cgd[i * kMaxGate + j] * V[p * g + j];
-            xu[i] = s;
+        PixRec *o = pr + p;
+        for (int q = dot; q < kMaxDot; q += NM) {
+            o->g0[q] = (q < NM) ? g0 : 0.0;
+            o->n0[q] = (int16_t)((q < NM) ? n0 : 0);
         }
-        // analytic minimum: open x = x_u; closed adds (N_hat - 1^T x_u) C_dd 1 / (1^T C_dd 1)
-        double lam = 0.0;
-        if (CLOSED) {
-            double sx = 0.0;
-#pragma unroll
-            for (int i = 0; i < NM; ++i) sx += xu[i];
-            lam = ((double)dr->nhat - sx) / dr->one_c;
+        if (dot == 0) {
+            o->u0 = u0;
+            o->free = fm;
+            o->k = k;
+            o->flags = flags | cflags;
+            o->pad = 0;
+            if (flags_out) flags_out[p] = flags | (cflags & 4);
+            if (cflags & 4) atomicAdd(&cnt[2], 1ull);
+            if (flags & 1) atomicAdd(&cnt[1], 1ull);
+            if (flags & 2) atomicAdd(&cnt[3], 1ull);
+            atomicAdd(&cnt[0], 1ull);
         }
-        bool feasible = true;
-#pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            x[i] = (i < n) ? xu[i] + lam * dr->c[i] : 0.0;
-            feasible &= x[i] >= 0.0;
-        }
-        bool solved_qp = false;
-        if (CLOSED && dr->nhat == 0) {
-            // x = 0 is the only admissible point of a closed empty array, so
-            // it is the QP's solution whenever the analytic one is negative
-            solved_qp = !feasible;
-#pragma unroll
-            for (int i = 0; i < NM; ++i) x[i] = 0.0;
-            feasible = true;
-        }
-        int flags = solved_qp ? 1 : 0;
-        if (!feasible) {
-            // the QP of Sec. 3.1.2, solved exactly in this lane
-            const bool ok = qp_solve<NM, CLOSED>(dr, xu, x);
-            flags = ok ? 1 : 3;
-        }
-        int dbl = 0;
-        finish_pixel<NM, CLOSED>(dr, x, xu, flags, pr + p, &dbl);
-        if (x_out) {
-#pragma unroll
-            for (int i = 0; i < NM; ++i)
-                if (i < n) x_out[p * n + i] = x[i];
-        }
-        if (flags_out) flags_out[p] = flags | (dbl ? 4 : 0);
-        if (dbl) atomicAdd((unsigned long long *)&sc[2], 1ull);
-        if (flags & 1) atomicAdd((unsigned long long *)&sc[1], 1ull);
-        if (flags & 2) atomicAdd((unsigned long long *)&sc[3], 1ull);
-        atomicAdd((unsigned long long *)&sc[0], 1ull);
+        if (x_out && is_dot) x_out[p * n + dot] = x;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        block_add_counter(counters, C_PIXELS, sc[0]);
-        block_add_counter(counters, C_QP, sc[1]);
-        block_add_counter(counters, C_DOUBLED, sc[2]);
-        block_add_counter(counters, C_QP_FAIL, sc[3]);
+        block_add_counter(counters, C_PIXELS, cnt[0]);
+        block_add_counter(counters, C_QP, cnt[1]);
+        block_add_counter(counters, C_DOUBLED, cnt[2]);
+        block_add_counter(counters, C_QP_FAIL, cnt[3]);
     }
 }
 
@@ -170,13 +295,16 @@ hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *p
                         int64_t *counters, int n_dot, bool closed, hipStream_t s,
                         double *x_out, int32_t *flags_out)
 {
-    const dim3 grid((unsigned)((P + 255) / 256)), block(256);
+    if (P <= 0) return hipSuccess;
+    const dim3 block(256);
     if (closed)
-        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>), grid, block, 0, s, dr, V, P,
-                                                 pr, counters, x_out, flags_out));
+        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>),
+                                                 dim3((unsigned)((P * NM_ + 255) / 256)), block, 0,
+                                                 s, dr, V, P, pr, counters, x_out, flags_out));
     else
-        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, false>), grid, block, 0, s, dr, V,
-                                                 P, pr, counters, x_out, flags_out));
+        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, false>),
+                                                 dim3((unsigned)((P * NM_ + 255) / 256)), block, 0,
+                                                 s, dr, V, P, pr, counters, x_out, flags_out));
     return hipGetLastError();
 }
 
