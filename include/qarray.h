@@ -174,18 +174,25 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
 size_t qa_saved_bytes(int64_t P, int32_t n_dot);
 
 /* A batch of independent diagrams (the dataset-generation use of Sec. 1)
- * in one launch sequence.  Diagram d uses probs[d] (its own N, G, mode,
- * N_hat, kT, t) and the gate voltages V_dev + v_offsets[d] (P_d x G_d,
- * FP64, P_d = out_offsets[d+1]/N_d - out_offsets[d]/N_d rows ... see below).
- *   v_offsets   : host, n_diag entries, element offset of diagram d's V.
- *   pix_counts  : host, n_diag entries, P_d.
- *   out_offsets : host, n_diag entries, element offset of diagram d's
- *                 output rows (P_d x N_d) in n_out_dev / nbar_out_dev.
- *   n_out_dev   : device int32, receives the T = 0 ground state of every
- *                 diagram (argmin over the candidate set).
- *   nbar_out_dev: device FP64 or NULL; receives the softargmin of diagrams
- *                 with kT > 0 (rows of kT = 0 diagrams get n* as FP64).
- * All diagrams share the precision of probs[0] (FP64 in this build). */
+ * in one graph-captured launch sequence.  Diagram d has its own problem
+ * probs[d] (N_d, G_d, mode, N_hat, kT, t; precision is ignored, every
+ * energy is FP64) and its own P_d pixels.
+ *   V_dev       : device FP64; diagram d's voltages are the P_d x G_d
+ *                 row-major block starting at element v_offsets[d].
+ *   v_offsets   : host, n_diag entries (elements, not bytes).
+ *   pix_counts  : host, n_diag entries, P_d >= 0.
+ *   out_offsets : host, n_diag entries; diagram d's outputs are the
+ *                 P_d x N_d row-major block starting at element
+ *                 out_offsets[d] of n_out_dev and of nbar_out_dev.
+ *   n_out_dev   : device int32; the T = 0 ground state (argmin over the
+ *                 candidate set) of every pixel of every diagram.
+ *   nbar_out_dev: device FP64 or NULL; the softargmin of diagrams with
+ *                 kT > 0 (for kT = 0 diagrams, n* converted to FP64).
+ *   stats       : host or NULL; summed over the batch (waits for the stream).
+ * Every problem is validated as for qa_ground_state before any device work;
+ * blocks must lie inside the caller's buffers (not checked: device sizes
+ * are unknown to the library).  Returns QA_E_SHAPE for n_diag < 0 or a
+ * negative offset or count. */
 qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
                                   const int64_t *v_offsets, const int64_t *pix_counts,
                                   const int64_t *out_offsets, int32_t *n_out_dev,

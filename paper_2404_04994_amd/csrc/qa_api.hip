@@ -74,6 +74,8 @@ struct Workspace {
     DiagRec *stage = nullptr;           // kRing pinned host records
     hipEvent_t stage_ev[kRing] = {};
     int stage_next = 0;
+    // the inputs last copied into dr (a call with the same problem reuses them)
+    std::vector<unsigned char> dr_inputs;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
 };
 
@@ -237,16 +239,25 @@ qa_status upload_diag(Workspace *w, const qa_problem *pb)
     w->stage_next = (slot + 1) % Workspace::kRing;
     QA_HIP(hipEventSynchronize(w->stage_ev[slot]));
     fill_diag(pb, &w->stage[slot]);
+    // the same problem as the previous call on this stream: its inputs are
+    // still in w->dr (only the prologue's outputs follow them there)
+    if (w->dr_inputs.size() == kDiagInputBytes &&
+        std::memcmp(w->dr_inputs.data(), &w->stage[slot], kDiagInputBytes) == 0)
+        return QA_OK;
     QA_HIP(hipMemcpyAsync(w->dr, &w->stage[slot], kDiagInputBytes, hipMemcpyHostToDevice,
                           w->stream));
     QA_HIP(hipEventRecord(w->stage_ev[slot], w->stream));
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(&w->stage[slot]);
+    w->dr_inputs.assign(b, b + kDiagInputBytes);
     return QA_OK;
 }
 
 qa_status grow_single(Workspace *w, int64_t P)
 {
     qa_status st;
+    DiagRec *dr0 = w->dr;
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
+    if (w->dr != dr0) w->dr_inputs.clear();
     if ((st = grow(w, w->pr, w->pr_cap, P))) return st;
     if ((st = grow(w, w->flag_list, w->flag_cap, P))) return st;
     return QA_OK;
@@ -433,7 +444,9 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
         return fail(QA_E_NULL, "V_dev, grad_nbar_dev or saved_dev is NULL");
     Workspace *w;
     if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    DiagRec *dr0 = w->dr;
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
+    if (w->dr != dr0) w->dr_inputs.clear();
     const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + 4096;
     if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
     if ((st = upload_diag(w, prob))) return st;

@@ -8,7 +8,8 @@
 //              the candidate description (n0, free mask, k) and the FP64
 //              gradient g0 = A (n0 - x_u) and energy U(n0) at the base state.
 //   SavedRec : per pixel, the softargmin state the adjoint needs (the
-//              caller-owned "saved" buffer of qa_soft_charge).
+//              caller-owned "saved" buffer of qa_soft_charge): candidate
+//              set, smallest energy, normaliser and mean offset; no energies.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -73,7 +74,8 @@ struct alignas(8) PixRec {
 
 struct alignas(8) SavedRec {
     double emin;          // smallest candidate energy
-    double logZ;          // log sum exp(-(E - emin)/kT)
+    double Z;             // sum exp(-(E - emin)/kT) (>= 1)
+    double nb[kMaxDot];   // <n> - n0 = sum_s pi_s 1_s (zero beyond n)
     int16_t n0[kMaxDot];
     uint32_t free;
     int32_t k;

@@ -322,6 +322,8 @@ __global__ __launch_bounds__(256) void k_score_fp64(const DiagRec *__restrict__ 
     constexpr int G = 1 << LG;
     __shared__ double sA[kMaxDot * kMaxDot];
     __shared__ unsigned long long sc[2];
+    // list mode with an empty list (the usual case): nothing to do
+    if (list && *list_count == 0) return;
     for (int i = threadIdx.x; i < kMaxDot * kMaxDot; i += blockDim.x) sA[i] = dr->A[i];
     if (threadIdx.x < 2) sc[threadIdx.x] = 0;
     __syncthreads();
@@ -503,7 +505,10 @@ __global__ __launch_bounds__(256) void k_soft_fwd(const DiagRec *__restrict__ dr
             if (saved) {
                 SavedRec *o = saved + p;
                 o->emin = emin;
-                o->logZ = log(Z);
+                o->Z = Z;
+#pragma unroll
+                for (int i = 0; i < NM; ++i) o->nb[i] = sv[i] / Z;
+                for (int i = NM; i < kMaxDot; ++i) o->nb[i] = 0.0;
                 for (int i = 0; i < kMaxDot; ++i) o->n0[i] = r->n0[i];
                 o->free = r->free;
                 o->k = r->k;
@@ -533,6 +538,11 @@ hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, doubl
 // ---------------------------------------------------------------------------
 constexpr int kBwdMaxDot = 12;
 
+// One walk per pixel: the forward pass saved E_min, Z and nb, so the weights
+// pi_s = exp(-(E_s - E_min)/kT) / Z follow from the recomputed energies.
+// Per-pixel outer products are accumulated in registers across the group's
+// pixels (lane i: row i of the dL/dA sum; lane j: gate column j of the
+// dL/dC_gd sum) and reach LDS and HBM once per block.
 template <int LG, int NM>
 __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr,
                                                   const double *__restrict__ V, int64_t P,
@@ -545,7 +555,9 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
 {
     constexpr int G = 1 << LG;
     constexpr int NU = 1 << (NM < kBwdMaxDot ? NM : kBwdMaxDot);
+    constexpr int KG = (kMaxGate + G - 1) / G;  // gate columns per lane
     __shared__ double sA[kMaxDot * kMaxDot];
+    __shared__ double sCgd[kMaxDot * kMaxGate];
     __shared__ double sU[NU];
     __shared__ double sdA[kMaxDot * kMaxDot];
     __shared__ double sdG[kMaxDot * kMaxGate];
@@ -553,25 +565,36 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
         sA[i] = dr->A[i];
         sdA[i] = 0.0;
     }
+    for (int i = threadIdx.x; i < kMaxDot * kMaxGate; i += blockDim.x) {
+        sCgd[i] = dr->Cgd[i];
+        sdG[i] = 0.0;
+    }
     for (int i = threadIdx.x; i < NU; i += blockDim.x) sU[i] = 0.0;
-    for (int i = threadIdx.x; i < kMaxDot * kMaxGate; i += blockDim.x) sdG[i] = 0.0;
     __syncthreads();
     const int n = dr->n, g = dr->g;
     const double kT = dr->kT;
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
+    double rowA[NM], colG[KG][NM];
+#pragma unroll
+    for (int j = 0; j < NM; ++j) rowA[j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < KG; ++r)
+#pragma unroll
+        for (int i = 0; i < NM; ++i) colG[r][i] = 0.0;
     for (int64_t p = gid; p < P; p += ngroups) {
         const SavedRec *sr = saved + p;
-        double xu[NM], z[NM], g0[NM], gb[NM];
+        double z[NM], g0[NM], gb[NM];
+        double gnb = 0.0;
 #pragma unroll
         for (int i = 0; i < NM; ++i) {
             double s = 0.0;
             if (i < n)
-                for (int j = 0; j < g; ++j) s += dr->Cgd[i * kMaxGate + j] * V[p * g + j];
-            xu[i] = s;
+                for (int j = 0; j < g; ++j) s += sCgd[i * kMaxGate + j] * V[p * g + j];
             z[i] = (i < n) ? (double)sr->n0[i] - s : 0.0;
             gb[i] = (i < n) ? gbar[p * n + i] : 0.0;
+            gnb += gb[i] * sr->nb[i];
         }
         double u0 = 0.0;
 #pragma unroll
@@ -585,42 +608,15 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
         u0 *= 0.5;
         const uint32_t fm = sr->free;
         const int k = sr->k;
-        const double emin = sr->emin;
+        const double emin = sr->emin, Z = sr->Z;
         const int m = __popc(fm);
         const uint64_t pos = free_positions(fm);
         const int chunk_log = m > LG ? m - LG : 0;
         const bool active = (m >= LG) || (lane < (1 << m));
         const uint32_t c0 = (uint32_t)lane << chunk_log;
         const int steps = 1 << chunk_log;
-        double y[NM];
-        // pass 1: normaliser and mean offset
-        double zsum = 0.0, nb[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) nb[i] = 0.0;
-        if (active) {
-            uint32_t s = pdep_mask(c0 ^ (c0 >> 1), fm);
-            int pc = __popc(s);
-            walk_start<NM>(sA, s, y);
-            for (int step = 0; step < steps; ++step) {
-                if (step) walk_flip<NM>(sA, pos, step, s, pc, y);
-                if (k < 0 || pc == k) {
-                    const double w = exp(-(walk_energy<NM>(g0, y, u0, s) - emin) / kT);
-                    zsum += w;
-#pragma unroll
-                    for (int i = 0; i < NM; ++i)
-                        if (s >> i & 1u) nb[i] += w;
-                }
-            }
-        }
-        const double Z = group_sum<LG>(zsum);
-        double gnb = 0.0;
-#pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            nb[i] = group_sum<LG>(nb[i]) / Z;
-            gnb += gb[i] * nb[i];
-        }
-        // pass 2: ubar_s, m_p and u_s
-        double mv[NM];
+        // ubar_s, m_p and u_s
+        double y[NM], mv[NM];
 #pragma unroll
         for (int i = 0; i < NM; ++i) mv[i] = 0.0;
         if (active) {
@@ -645,33 +641,51 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
         }
 #pragma unroll
         for (int i = 0; i < NM; ++i) mv[i] = group_sum<LG>(mv[i]);
-        if (lane == 0) {
-            double dx[NM];
+        double dx[NM];
 #pragma unroll
-            for (int i = 0; i < NM; ++i) {
-                double s = 0.0;
+        for (int i = 0; i < NM; ++i) {
+            double s = 0.0;
 #pragma unroll
-                for (int j = 0; j < NM; ++j) s += sA[i * kMaxDot + j] * mv[j];
-                dx[i] = -s;
-            }
+            for (int j = 0; j < NM; ++j) s += sA[i * kMaxDot + j] * mv[j];
+            dx[i] = -s;
+        }
+        // lane i < n: row i of 1/2 (z m^T + m z^T)
+        double zi = 0.0, mi = 0.0;
 #pragma unroll
-            for (int i = 0; i < NM; ++i)
+        for (int i = 0; i < NM; ++i)
+            if (i == lane) { zi = z[i]; mi = mv[i]; }
+        if (lane < n) {
 #pragma unroll
-                for (int j = 0; j < NM; ++j)
-                    if (i < n && j < n)
-                        atomicAdd(&sdA[i * kMaxDot + j], 0.5 * (z[i] * mv[j] + mv[i] * z[j]));
-            for (int j = 0; j < g; ++j) {
+            for (int j = 0; j < NM; ++j) rowA[j] += 0.5 * (zi * mv[j] + mi * z[j]);
+        }
+        // gate column j: dL/dC_gd += dx V_j, dL/dV_j = sum_i C_gd,ij dx_i
+#pragma unroll
+        for (int r = 0; r < KG; ++r) {
+            const int j = lane + G * r;
+            if (j < g) {
                 const double vj = V[p * g + j];
                 double gv = 0.0;
 #pragma unroll
                 for (int i = 0; i < NM; ++i) {
-                    if (i < n) {
-                        atomicAdd(&sdG[i * kMaxGate + j], dx[i] * vj);
-                        gv += dr->Cgd[i * kMaxGate + j] * dx[i];
-                    }
+                    colG[r][i] += dx[i] * vj;
+                    gv += sCgd[i * kMaxGate + j] * dx[i];
                 }
                 if (gradV) gradV[p * g + j] = gv;
             }
+        }
+    }
+    if (lane < n) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j)
+            if (j < n && rowA[j] != 0.0) atomicAdd(&sdA[lane * kMaxDot + j], rowA[j]);
+    }
+#pragma unroll
+    for (int r = 0; r < KG; ++r) {
+        const int j = lane + G * r;
+        if (j < g) {
+#pragma unroll
+            for (int i = 0; i < NM; ++i)
+                if (i < n && colG[r][i] != 0.0) atomicAdd(&sdG[i * kMaxGate + j], colG[r][i]);
         }
     }
     __syncthreads();

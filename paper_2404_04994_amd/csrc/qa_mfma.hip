@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
     __shared__ int sband[4][kMaxBand];
     __shared__ int sbandn[4];
     __shared__ double sG64[4][kMaxDot];
+    __shared__ uint2 sCt[4][256];  // per wave: BF16 parts of C(c_hi) of its pixel
     __shared__ unsigned long long sflag, sover, sgap;
     for (int e = threadIdx.x; e < 128; e += blockDim.x) {
         sT1[e / 8][e % 8] = dr->T1[e / 8][e % 8];
@@ -125,17 +126,33 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
         }
     }
 
+    // Persistent waves: wave w scores pixels w, w + nwaves, ...  Lane i < 16
+    // holds g0_i and n0_i of its pixel (vector loads, one pixel ahead).
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     int64_t nflag = 0, nover = 0, ngap = 0;
+    const int li = lane & 15;
+    double gnext = 0.0;
+    int nnext = 0;
+    if (wave < P) {
+        gnext = pr[wave].g0[li];
+        nnext = pr[wave].n0[li];
+    }
     for (int64_t pw = wave; pw < P; pw += nwaves) {
-        const int64_t p = __builtin_amdgcn_readfirstlane((int)pw);
-        const PixRec *r = pr + p;
+        const int64_t p = pw;
+        const double gcur = gnext;
+        const int ncur = nnext;
+        if (pw + nwaves < P) {
+            gnext = pr[pw + nwaves].g0[li];
+            nnext = pr[pw + nwaves].n0[li];
+        }
+        // g0 beyond n is zero in the record; every lane gets all sixteen
+        const float gl = (float)gcur;
         float g[16];
         float gabs = 0.0f;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            g[i] = (i < n) ? (float)r->g0[i] : 0.0f;
+            g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i));
             gabs += fabsf(g[i]);
         }
         // per-lane row constants: G1 = g_lo + A_LH b_hi(row bits), P1 = b_hi(row)^T g_hi
@@ -146,15 +163,46 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if (mrow >> j & 1) P1 += g[8 + j];
-
-        // build the A operand of row tile rt for this lane
-        auto build_a = [&](int rt, Pack8 &a, float (&af)[3]) {
-            float P2 = 0.0f;
+        // split-BF16 forms: the lane builds low dots 2q and 2q + 1 of its row
+        float G1a = G1[0], G1b = G1[1];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (rt >> j & 1) P2 += g[12 + j];
-            const float C = (P1 + P2) + sH[rt * 16 + mrow];
+        for (int d = 1; d < 4; ++d)
+            if (q == d) { G1a = G1[2 * d]; G1b = G1[2 * d + 1]; }
+        // and the wave tabulates the constant chunk of every high index once:
+        // C(c_hi) = b_hi^T g_hi + 1/2 b_hi^T A_HH b_hi as three BF16 parts,
+        // dword 0 = (C_1, C_2), dword 1 = (C_3, 1)
+        uint2 *ctab = sCt[threadIdx.x >> 6];
+        if (PREC != kPrecFP32) {
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int rt = q + 4 * e4;
+                float P2 = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (rt >> j & 1) P2 += g[12 + j];
+                const float C = (P1 + P2) + sH[rt * 16 + mrow];
+                const float c1 = trunc16(C);
+                const float cr = C - c1;
+                const float c2 = trunc16(cr);
+                ctab[rt * 16 + mrow] = make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+
+        // Build the A operand of row tile rt for this lane.  Split-BF16 forms:
+        // the four lanes of a row share the work.  Lane (q, row) splits
+        // g'_{2q} and g'_{2q+1} into their BF16 parts (dword p = part p of the
+        // pair) and forms dword q of the constant chunk (C parts and ones);
+        // a 4 x 4 transpose of those dwords across the four 16-lane rows
+        // (two v_permlane32_swap, two v_permlane16_swap) leaves lane (q, row)
+        // with part q of g'_0..g'_7 (q < 3) or the constant chunk (q = 3).
+        auto build_a = [&](int rt, Pack8 &a, float (&af)[3]) {
             if (PREC == kPrecFP32) {
+                float P2 = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (rt >> j & 1) P2 += g[12 + j];
+                const float C = (P1 + P2) + sH[rt * 16 + mrow];
                 float v0 = 0.0f, v1 = 0.0f;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -167,40 +215,36 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
                 af[1] = v1;
                 af[2] = (q == 0) ? C : (q == 1 ? 1.0f : 0.0f);
             } else {
-                float v[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = G1[j] + sT2[rt][j];
+                const float v0 = G1a + sT2[rt][2 * q];
+                const float v1 = G1b + sT2[rt][2 * q + 1];
+                uint32_t R0, R1, R2;
                 if (PREC == kPrecX3) {
-                    // exact three-way split: part q of v is the BF16 truncation
-                    // of v after removing q leading BF16 parts
-                    const uint32_t m1 = q >= 1 ? 0xFFFF0000u : 0u;
-                    const uint32_t m2 = q >= 2 ? 0xFFFF0000u : 0u;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        v[j] -= __uint_as_float(fbits(v[j]) & m1);
-                        v[j] -= __uint_as_float(fbits(v[j]) & m2);
-                        v[j] = trunc16(v[j]);
-                    }
+                    // exact three-way truncation split: v = p0 + p1 + p2
+                    const float a0 = trunc16(v0), b0 = trunc16(v1);
+                    const float r0 = v0 - a0, s0 = v1 - b0;
+                    const float a1 = trunc16(r0), b1 = trunc16(s0);
+                    R0 = pack2(a0, b0);
+                    R1 = pack2(a1, b1);
+                    R2 = pack2(r0 - a1, s0 - b1);
                 } else {
                     // two round-to-nearest parts; chunk 2 unused
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const float s1 = rne16(v[j]);
-                        const float s2 = rne16(v[j] - s1);
-                        v[j] = (q == 0) ? s1 : (q == 1 ? s2 : 0.0f);
-                    }
+                    const float a0 = rne16(v0), b0 = rne16(v1);
+                    R0 = pack2(a0, b0);
+                    R1 = pack2(rne16(v0 - a0), rne16(v1 - b0));
+                    R2 = 0u;
                 }
-                if (q == 3) {
-                    const float c1 = trunc16(C);
-                    const float cr = C - c1;
-                    const float c2 = trunc16(cr);
-                    const float c3 = cr - c2;  // exact in BF16
-                    v[0] = c1; v[1] = c2; v[2] = c3;
-                    v[3] = 1.0f; v[4] = 1.0f; v[5] = 1.0f;
-                    v[6] = 0.0f; v[7] = 0.0f;
-                }
-#pragma unroll
-                for (int d = 0; d < 4; ++d) a.u[d] = pack2(v[2 * d], v[2 * d + 1]);
+                const uint2 cw = ctab[rt * 16 + mrow];
+                uint32_t R3 = (q == 2) ? 0x3F803F80u : 0u;
+                R3 = (q == 1) ? cw.y : R3;
+                R3 = (q == 0) ? cw.x : R3;
+                const auto t02 = __builtin_amdgcn_permlane32_swap(R0, R2, false, false);
+                const auto t13 = __builtin_amdgcn_permlane32_swap(R1, R3, false, false);
+                const auto u01 = __builtin_amdgcn_permlane16_swap(t02[0], t13[0], false, false);
+                const auto u23 = __builtin_amdgcn_permlane16_swap(t02[1], t13[1], false, false);
+                a.u[0] = u01[0];
+                a.u[1] = u01[1];
+                a.u[2] = u23[0];
+                a.u[3] = u23[1];
             }
         };
         auto tile = [&](const Pack8 &a, const float (&af)[3], int ct) -> f32x4_t {
@@ -282,7 +326,7 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
                 const uint32_t chi = (uint32_t)(rtw * 16 + row);
                 const uint32_t clo = (uint32_t)(ct * 16 + (winner & 15));
                 const uint32_t b = clo | (chi << 8);
-                n_out[p * n + lane] = (int32_t)r->n0[lane] + (int32_t)((b >> lane) & 1u);
+                n_out[p * n + lane] = ncur + (int32_t)((b >> lane) & 1u);
             }
             continue;
         }
@@ -326,7 +370,7 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
             continue;
         }
         double *g64 = sG64[threadIdx.x >> 6];
-        if (lane < kMaxDot) g64[lane] = (lane < n) ? r->g0[lane] : 0.0;
+        if (lane < kMaxDot) g64[lane] = gcur;
         __builtin_amdgcn_wave_barrier();
         double b1 = INFINITY, b2 = INFINITY;
         uint32_t c1 = 0;
@@ -358,7 +402,7 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
                 b2 = fmin(b2, ob1);
             }
         }
-        if (lane < n) n_out[p * n + lane] = (int32_t)r->n0[lane] + (int32_t)((c1 >> lane) & 1u);
+        if (lane < n) n_out[p * n + lane] = ncur + (int32_t)((c1 >> lane) & 1u);
         if (lane == 0 && b2 - b1 < 1e-9) ++ngap;
     }
     if (lane == 0) {
@@ -378,13 +422,40 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
     }
 }
 
+// blocks of 256 threads of the given scorer form that fit on the device at once
+static int resident_blocks(int prec)
+{
+    static int cache[4][64];  // [prec][device] (0 = not yet known)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || prec < 1 || prec > 3) return 0;
+    int &c = cache[prec][dev];
+    if (c) return c;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (prec == kPrecFP32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_mfma<kPrecFP32>, 256, 0);
+    else if (prec == kPrecX3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_mfma<kPrecX3>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_mfma<kPrecX2>, 256, 0);
+    if (e != hipSuccess || per_cu <= 0) return 0;
+    c = cus * per_cu;
+    return c;
+}
+
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
                              int32_t *n_out, int32_t *flag_list, int64_t *counters, int n_dot,
                              hipStream_t s)
 {
     if (n_dot < 9 || n_dot > 16) return hipErrorInvalidValue;
-    int64_t blocks = (P + 3) / 4;  // one wave per pixel, four waves per block
-    if (blocks > 65536) blocks = 65536;
+    if (P <= 0) return hipSuccess;
+    // persistent waves: as many blocks as the chip keeps resident, at most
+    // one wave per pixel
+    int64_t blocks = (P + 3) / 4;
+    const int resident = resident_blocks(prec);
+    if (resident > 0 && blocks > resident) blocks = resident;
     const dim3 grid((unsigned)blocks), block(256);
     switch (prec) {
     case kPrecFP32:
