@@ -13,6 +13,7 @@ roofline of the dominant kernel and the FP64 oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--precision bf16x3]
     python bench.py --mode kernel    # only the headline calls (for rocprofv3)
+    python bench.py --mode adjoint   # only the adjoint forward + backward calls
     python bench.py --mode copy      # plain HBM copy for counter calibration
 """
 from __future__ import annotations
@@ -72,6 +73,36 @@ def direct_gs(qa, d, V, out, precision, torch):
     return call
 
 
+def direct_soft(qa, cdd, cgd, V, kT, gbar, torch):
+    """Softargmin forward and forward + backward as direct ABI calls, with
+    marshalling and output allocation hoisted out of the timed loop."""
+    import ctypes as C
+    lib = qa.load()
+    pb, keep = qa.make_problem(cdd, cgd, False, 0, kT, 1.0, "fp64")
+    P, n, g = V.shape[0], pb.n_dot, pb.n_gate
+    nbar = torch.empty((P, n), dtype=torch.float64, device="cuda")
+    saved = torch.empty(qa.saved_bytes(P, n), dtype=torch.uint8, device="cuda")
+    dC = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    dG = torch.empty((n, g), dtype=torch.float64, device="cuda")
+    dV = torch.empty_like(V)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ptr = [C.c_void_p(t.data_ptr()) for t in (V, nbar, saved, gbar, dC, dG, dV)]
+
+    def fwd():
+        st = lib.qa_soft_charge(C.byref(pb), ptr[0], P, ptr[1], ptr[2], None, stream)
+        if st:
+            raise qa.QArrayError(st, lib.qa_last_error().decode())
+
+    def fwdbwd():
+        fwd()
+        st = lib.qa_soft_charge_backward(C.byref(pb), ptr[0], P, ptr[3], ptr[2], ptr[4], ptr[5],
+                                         ptr[6], stream)
+        if st:
+            raise qa.QArrayError(st, lib.qa_last_error().decode())
+    fwd.keep = fwdbwd.keep = (pb, keep, nbar, saved, dC, dG, dV)
+    return fwd, fwdbwd
+
+
 def run_copy(torch):
     """256 MiB device-to-device copy: FETCH_SIZE/WRITE_SIZE calibration."""
     n = 256 << 20
@@ -112,7 +143,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x2", "fp32", "fp64"])
-    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "copy"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "adjoint", "copy"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -137,6 +168,15 @@ def main():
     out = torch.empty((d.P, d.n_dot), dtype=torch.int32, device="cuda")
     call = direct_gs(qa, d, V, out, args.precision, torch)
 
+    if args.mode == "adjoint":
+        a = W.adjoint_case(400)
+        Va = torch.as_tensor(a.V, device="cuda")
+        gb = torch.randn((Va.shape[0], 8), dtype=torch.float64, device="cuda")
+        _, fwdbwd = direct_soft(qa, a.cdd[:8, :8], a.cgd[:8, :], Va, a.kT, gb, torch)
+        log("adjoint mode: %d forward + backward calls" % args.steps)
+        timed_calls(fwdbwd, args.steps, args.warmup, torch)
+        log("done")
+        return
     if args.mode == "kernel":
         log("kernel mode: %d headline calls, precision %s" % (args.steps, args.precision))
         timed_calls(call, args.steps, args.warmup, torch)
@@ -296,18 +336,19 @@ def run_extras(qa, W, torch, d, V, out, args):
     a = W.adjoint_case(400)
     Va = torch.as_tensor(a.V, device="cuda")
     cdd8, cgd8 = a.cdd[:8, :8], a.cgd[:8, :]
-    gb = torch.randn((Va.shape[0], 8), dtype=torch.float64, device="cuda")
+    gb = torch.randn((Va.shape[0], 8), dtype=torch.float64, device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(5))
+    fwd_d, fwdbwd_d = direct_soft(qa, cdd8, cgd8, Va, a.kT, gb, torch)
+    wf = timed_calls(fwd_d, steps, 3, torch)
+    wb = timed_calls(fwdbwd_d, steps, 3, torch)
 
-    def fwd():
-        return qa.soft_charge(cdd8, cgd8, Va, a.kT)
-
-    def fwdbwd():
+    def fwdbwd_py():  # through the Python wrappers (tensor allocation per call)
         nb, saved = qa.soft_charge(cdd8, cgd8, Va, a.kT)
         qa.soft_charge_backward(cdd8, cgd8, Va, a.kT, gb, saved)
-    wf = timed_calls(fwd, steps, 3, torch)
-    wb = timed_calls(fwdbwd, steps, 3, torch)
+    wp = timed_calls(fwdbwd_py, steps, 3, torch)
     res["adjoint_8dot_sensor"] = {"fwd_ms": round(1e3 * wf / steps, 4),
                                   "fwd_bwd_ms_per_diagram": round(1e3 * wb / steps, 4),
+                                  "fwd_bwd_ms_python_wrappers": round(1e3 * wp / steps, 4),
                                   "pixels": int(Va.shape[0])}
     log("adjoint: %s" % res["adjoint_8dot_sensor"])
     # ragged dataset batch: 4096 diagrams of 2..8 dots, 64 x 64 pixels each

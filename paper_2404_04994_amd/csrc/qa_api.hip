@@ -450,8 +450,10 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
     const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + 4096;
     if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
     if ((st = upload_diag(w, prob))) return st;
-    QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream));
     double *accA = w->acc, *accG = accA + kMaxDot * kMaxDot, *accU = accG + kMaxDot * kMaxGate;
+    QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream, accA,
+                       (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate +
+                           ((int64_t)1 << prob->n_dot)));
     QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, accA, accG,
                            accU, grad_V_dev, prob->n_dot, w->stream));
     QA_HIP(launch_soft_bwd_final(w->dr, accA, accG, accU, grad_cdd_dev, grad_cgd_dev, w->stream));

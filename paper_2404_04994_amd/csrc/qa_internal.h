@@ -97,8 +97,10 @@ struct alignas(8) BatchHdr {
 // error of the launch.
 // -------------------------------------------------------------------------
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s);
-// prologue of n_diag diagrams; also zeroes the C_NUM counters when given
-hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s);
+// prologue of n_diag diagrams; also zeroes the C_NUM counters and the nzero
+// doubles at zero when given
+hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s,
+                       double *zero = nullptr, int64_t nzero = 0);
 // setup of every pixel; x_out (P x N) / flags_out (P) optional copies of x*
 hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
                         int64_t *counters, int n_dot, bool closed, hipStream_t s,
@@ -113,6 +115,8 @@ hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int
                              int n_dot, hipStream_t s);
 hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
                            SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s);
+// adjoint partial sums into accA (kMaxDot^2), accG (kMaxDot x kMaxGate) and
+// accU (2^n), which must be zero on entry
 hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P,
                            const double *gbar, const SavedRec *saved, double *accA,
                            double *accG, double *accU, double *gradV, int n_dot,

@@ -30,27 +30,26 @@ hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_zero_f64(double *p, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0;
-}
-
 // ---------------------------------------------------------------------------
 // K0: per-diagram prologue, one 256-thread block per diagram
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kPrepThreads) void k_prep(DiagRec *dr_all, int64_t *counters)
+__global__ __launch_bounds__(kPrepThreads) void k_prep(DiagRec *dr_all, int64_t *counters,
+                                                      double *zero, int64_t nzero)
 {
     __shared__ double M[kMaxDot * kMaxDot];
     __shared__ double red[8];
-    // the call's counters start at zero (no separate memset in the graph)
+    // the call's counters (and accumulators) start at zero: no separate
+    // memset or fill kernel in the launch sequence
     if (counters && blockIdx.x == 0 && threadIdx.x < C_NUM) counters[threadIdx.x] = 0;
+    if (zero && blockIdx.x == 0)
+        for (int64_t i = threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0.0;
     prep_body(dr_all + blockIdx.x, M, red);
 }
 
-hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s)
+hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s, double *zero,
+                       int64_t nzero)
 {
-    hipLaunchKernelGGL(k_prep, dim3(n_diag), dim3(kPrepThreads), 0, s, dr, counters);
+    hipLaunchKernelGGL(k_prep, dim3(n_diag), dim3(kPrepThreads), 0, s, dr, counters, zero, nzero);
     return hipGetLastError();
 }
 
@@ -399,6 +398,19 @@ __global__ __launch_bounds__(256) void k_score_fp64(const DiagRec *__restrict__ 
         else { constexpr int LG_ = 6, NM_ = 16; CALL; }                         \
     } while (0)
 
+// table form (n <= 8): groups of up to 16 lanes, CPL candidates per lane
+#define QA_DISPATCH_TAB(n, CALL)                                                 \
+    do {                                                                         \
+        if ((n) == 1) { constexpr int LG_ = 1, NM_ = 2, CPL_ = 1; CALL; }        \
+        else if ((n) == 2) { constexpr int LG_ = 2, NM_ = 2, CPL_ = 1; CALL; }   \
+        else if ((n) == 3) { constexpr int LG_ = 3, NM_ = 4, CPL_ = 1; CALL; }   \
+        else if ((n) == 4) { constexpr int LG_ = 4, NM_ = 4, CPL_ = 1; CALL; }   \
+        else if ((n) == 5) { constexpr int LG_ = 4, NM_ = 8, CPL_ = 2; CALL; }   \
+        else if ((n) == 6) { constexpr int LG_ = 4, NM_ = 8, CPL_ = 4; CALL; }   \
+        else if ((n) == 7) { constexpr int LG_ = 4, NM_ = 8, CPL_ = 8; CALL; }   \
+        else { constexpr int LG_ = 4, NM_ = 8, CPL_ = 16; CALL; }                \
+    } while (0)
+
 static unsigned group_blocks(int64_t items, int lg, int64_t cap)
 {
     const int64_t per_block = 256 >> lg;
@@ -517,12 +529,117 @@ __global__ __launch_bounds__(256) void k_soft_fwd(const DiagRec *__restrict__ dr
     }
 }
 
+// Candidates of a pixel with n <= 8 dots in the table form: lane `lane` of
+// a group of G takes compressed indices c = lane + G q, q < CPL, and
+//   U(n0 + 1_s) = U(n0) + g0 . 1_s + h(s),  h(s) = 1/2 s^T A s,
+// with h from the prologue's whole-box table (LDS).  Inadmissible slots
+// (past the set, or the wrong closed popcount) get +inf.
+template <int NM>
+__device__ __forceinline__ double tab_energy(const double *__restrict__ sH, const double (&g0)[NM],
+                                             double u0, uint32_t fm, int k, uint32_t c,
+                                             uint32_t &sq)
+{
+    const uint32_t count = 1u << __popc(fm);
+    const bool full = (fm & (fm + 1)) == 0;  // every dot free: s = c
+    sq = full ? c : pdep_mask(c, fm);
+    double E = INFINITY;
+    if (c < count && (k < 0 || __popc(sq) == k)) {
+        double L = u0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+            if (sq >> i & 1u) L += g0[i];
+        E = L + sH[sq];
+    }
+    return E;
+}
+
+template <int LG, int NM, int CPL>
+__device__ __forceinline__ void tab_energies(const double *__restrict__ sH, const double (&g0)[NM],
+                                             double u0, uint32_t fm, int k, int lane,
+                                             double (&e)[CPL], uint32_t (&st)[CPL])
+{
+#pragma unroll
+    for (int q = 0; q < CPL; ++q)
+        e[q] = tab_energy<NM>(sH, g0, u0, fm, k, (uint32_t)(lane + (q << LG)), st[q]);
+}
+
+template <int LG, int NM, int CPL>
+__global__ __launch_bounds__(256) void k_soft_fwd_tab(const DiagRec *__restrict__ dr,
+                                                      const PixRec *__restrict__ pr, int64_t P,
+                                                      double *__restrict__ nbar,
+                                                      SavedRec *__restrict__ saved,
+                                                      int64_t *__restrict__ counters)
+{
+    constexpr int G = 1 << LG;
+    __shared__ double sH[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sH[i] = dr->hs[i];
+    __syncthreads();
+    const int n = dr->n;
+    const double kT = dr->kT;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
+    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
+    for (int64_t p = gid; p < P; p += ngroups) {
+        const PixRec *r = pr + p;
+        double g0[NM];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) g0[i] = r->g0[i];
+        double e[CPL];
+        uint32_t st[CPL];
+        tab_energies<LG, NM, CPL>(sH, g0, r->u0, r->free, r->k, lane, e, st);
+        double lmin = e[0];
+#pragma unroll
+        for (int q = 1; q < CPL; ++q) lmin = fmin(lmin, e[q]);
+        const double emin = group_min<LG>(lmin);
+        double z = 0.0, sv[NM];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) sv[i] = 0.0;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            if (e[q] < INFINITY) {
+                const double w = exp(-(e[q] - emin) / kT);
+                z += w;
+#pragma unroll
+                for (int i = 0; i < NM; ++i)
+                    if (st[q] >> i & 1u) sv[i] += w;
+            }
+        }
+        const double Z = group_sum<LG>(z);
+#pragma unroll
+        for (int i = 0; i < NM; ++i) sv[i] = group_sum<LG>(sv[i]);
+        // lane i < n writes dot i; lane 0 the rest of the saved record
+        double svl = 0.0;
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+            if (i == lane) svl = sv[i];
+        if (lane < n) nbar[p * n + lane] = (double)r->n0[lane] + svl / Z;
+        if (saved) {
+            SavedRec *o = saved + p;
+            if (lane < kMaxDot) {
+                o->nb[lane] = (lane < n) ? svl / Z : 0.0;
+                o->n0[lane] = r->n0[lane];
+            }
+            if (lane == 0) {
+                o->emin = emin;
+                o->Z = Z;
+                o->free = r->free;
+                o->k = r->k;
+            }
+        }
+    }
+}
+
 hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
                            SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s)
 {
-    QA_DISPATCH_GROUP(n_dot, hipLaunchKernelGGL((k_soft_fwd<LG_, NM_>),
-                                                dim3(group_blocks(P, LG_, 8192)), dim3(256), 0, s,
-                                                dr, pr, P, nbar, saved, counters));
+    if (n_dot <= 8) {
+        QA_DISPATCH_TAB(n_dot, hipLaunchKernelGGL((k_soft_fwd_tab<LG_, NM_, CPL_>),
+                                                  dim3(group_blocks(P, LG_, 8192)), dim3(256), 0,
+                                                  s, dr, pr, P, nbar, saved, counters));
+    } else {
+        hipLaunchKernelGGL((k_soft_fwd<6, 16>), dim3(group_blocks(P, 6, 8192)), dim3(256), 0, s,
+                           dr, pr, P, nbar, saved, counters);
+    }
     return hipGetLastError();
 }
 
@@ -538,12 +655,13 @@ hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, doubl
 // ---------------------------------------------------------------------------
 constexpr int kBwdMaxDot = 12;
 
-// One walk per pixel: the forward pass saved E_min, Z and nb, so the weights
-// pi_s = exp(-(E_s - E_min)/kT) / Z follow from the recomputed energies.
-// Per-pixel outer products are accumulated in registers across the group's
-// pixels (lane i: row i of the dL/dA sum; lane j: gate column j of the
-// dL/dC_gd sum) and reach LDS and HBM once per block.
-template <int LG, int NM>
+// One pass over the candidates per pixel: the forward pass saved E_min, Z
+// and nb, so the weights pi_s = exp(-(E_s - E_min)/kT) / Z follow from the
+// recomputed energies (table form for n <= 8, CPL > 0; the Gray-code walk
+// otherwise).  The per-pixel outer products go to block sums in LDS, spread
+// over the lanes (lane i: row i of the dL/dA sum; lane j: gate column j of
+// the dL/dC_gd sum), and reach HBM once per block.
+template <int LG, int NM, int CPL>
 __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr,
                                                   const double *__restrict__ V, int64_t P,
                                                   const double *__restrict__ gbar,
@@ -555,15 +673,16 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
 {
     constexpr int G = 1 << LG;
     constexpr int NU = 1 << (NM < kBwdMaxDot ? NM : kBwdMaxDot);
-    constexpr int KG = (kMaxGate + G - 1) / G;  // gate columns per lane
     __shared__ double sA[kMaxDot * kMaxDot];
     __shared__ double sCgd[kMaxDot * kMaxGate];
     __shared__ double sU[NU];
     __shared__ double sdA[kMaxDot * kMaxDot];
     __shared__ double sdG[kMaxDot * kMaxGate];
+    __shared__ double sH[CPL > 0 ? 256 : 1];  // whole-box table h(s) (table form)
     for (int i = threadIdx.x; i < kMaxDot * kMaxDot; i += blockDim.x) {
         sA[i] = dr->A[i];
         sdA[i] = 0.0;
+        if (CPL > 0) sH[i] = dr->hs[i];
     }
     for (int i = threadIdx.x; i < kMaxDot * kMaxGate; i += blockDim.x) {
         sCgd[i] = dr->Cgd[i];
@@ -576,79 +695,91 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
-    double rowA[NM], colG[KG][NM];
-#pragma unroll
-    for (int j = 0; j < NM; ++j) rowA[j] = 0.0;
-#pragma unroll
-    for (int r = 0; r < KG; ++r)
-#pragma unroll
-        for (int i = 0; i < NM; ++i) colG[r][i] = 0.0;
     for (int64_t p = gid; p < P; p += ngroups) {
+        // keep the reads of A in LDS inside the loop: hoisted, they would
+        // hold N^2 doubles in registers for the whole kernel
+        asm volatile("" ::: "memory");
         const SavedRec *sr = saved + p;
+        // dot-wise quantities: lane d = lane mod NM computes dot d, then the
+        // group gathers the vectors (G >= NM)
+        const int d = lane & (NM - 1);
+        double zd = 0.0;
+        if (d < n) {
+            double s = 0.0;
+            for (int j = 0; j < g; ++j) s += sCgd[d * kMaxGate + j] * V[p * g + j];
+            zd = (double)sr->n0[d] - s;
+        }
         double z[NM], g0[NM], gb[NM];
         double gnb = 0.0;
 #pragma unroll
         for (int i = 0; i < NM; ++i) {
-            double s = 0.0;
-            if (i < n)
-                for (int j = 0; j < g; ++j) s += sCgd[i * kMaxGate + j] * V[p * g + j];
-            z[i] = (i < n) ? (double)sr->n0[i] - s : 0.0;
+            z[i] = __shfl(zd, i, G);
             gb[i] = (i < n) ? gbar[p * n + i] : 0.0;
             gnb += gb[i] * sr->nb[i];
         }
+        // g0 = A z, U(n0) = 1/2 z^T g0
+        double gd = 0.0;
+#pragma unroll
+        for (int j = 0; j < NM; ++j) gd += sA[d * kMaxDot + j] * z[j];
         double u0 = 0.0;
 #pragma unroll
         for (int i = 0; i < NM; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < NM; ++j) s += sA[i * kMaxDot + j] * z[j];
-            g0[i] = s;
-            u0 += z[i] * s;
+            g0[i] = __shfl(gd, i, G);
+            u0 += z[i] * g0[i];
         }
         u0 *= 0.5;
         const uint32_t fm = sr->free;
         const int k = sr->k;
         const double emin = sr->emin, Z = sr->Z;
+        // ubar_s, m_p and u_s
+        double mv[NM];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) mv[i] = 0.0;
+        auto add_candidate = [&](uint32_t s, double E) {
+            const double pi = exp(-(E - emin) / kT) / Z;
+            double gs = 0.0;
+#pragma unroll
+            for (int i = 0; i < NM; ++i)
+                if (s >> i & 1u) gs += gb[i];
+            const double ub = -(pi / kT) * (gs - gnb);
+#pragma unroll
+            for (int i = 0; i < NM; ++i)
+                if (s >> i & 1u) mv[i] += ub;
+            atomicAdd(&sU[s], ub);
+        };
+        if constexpr (CPL > 0) {
+#pragma unroll 2
+            for (int q = 0; q < CPL; ++q) {
+                uint32_t sq;
+                const double E = tab_energy<NM>(sH, g0, u0, fm, k, (uint32_t)(lane + (q << LG)), sq);
+                if (E < INFINITY) add_candidate(sq, E);
+            }
+        }
         const int m = __popc(fm);
         const uint64_t pos = free_positions(fm);
         const int chunk_log = m > LG ? m - LG : 0;
-        const bool active = (m >= LG) || (lane < (1 << m));
+        const bool active = CPL == 0 && ((m >= LG) || (lane < (1 << m)));
         const uint32_t c0 = (uint32_t)lane << chunk_log;
         const int steps = 1 << chunk_log;
-        // ubar_s, m_p and u_s
-        double y[NM], mv[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) mv[i] = 0.0;
+        double y[NM];
         if (active) {
             uint32_t s = pdep_mask(c0 ^ (c0 >> 1), fm);
             int pc = __popc(s);
             walk_start<NM>(sA, s, y);
             for (int step = 0; step < steps; ++step) {
                 if (step) walk_flip<NM>(sA, pos, step, s, pc, y);
-                if (k < 0 || pc == k) {
-                    const double pi = exp(-(walk_energy<NM>(g0, y, u0, s) - emin) / kT) / Z;
-                    double gs = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NM; ++i)
-                        if (s >> i & 1u) gs += gb[i];
-                    const double ub = -(pi / kT) * (gs - gnb);
-#pragma unroll
-                    for (int i = 0; i < NM; ++i)
-                        if (s >> i & 1u) mv[i] += ub;
-                    atomicAdd(&sU[s], ub);
-                }
+                if (k < 0 || pc == k) add_candidate(s, walk_energy<NM>(g0, y, u0, s));
             }
         }
 #pragma unroll
         for (int i = 0; i < NM; ++i) mv[i] = group_sum<LG>(mv[i]);
+        // dL/dx_u = -A m
+        double dd = 0.0;
+#pragma unroll
+        for (int j = 0; j < NM; ++j) dd -= sA[d * kMaxDot + j] * mv[j];
         double dx[NM];
 #pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < NM; ++j) s += sA[i * kMaxDot + j] * mv[j];
-            dx[i] = -s;
-        }
+        for (int i = 0; i < NM; ++i) dx[i] = __shfl(dd, i, G);
         // lane i < n: row i of 1/2 (z m^T + m z^T)
         double zi = 0.0, mi = 0.0;
 #pragma unroll
@@ -656,36 +787,19 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
             if (i == lane) { zi = z[i]; mi = mv[i]; }
         if (lane < n) {
 #pragma unroll
-            for (int j = 0; j < NM; ++j) rowA[j] += 0.5 * (zi * mv[j] + mi * z[j]);
+            for (int j = 0; j < NM; ++j)
+                if (j < n) atomicAdd(&sdA[lane * kMaxDot + j], 0.5 * (zi * mv[j] + mi * z[j]));
         }
         // gate column j: dL/dC_gd += dx V_j, dL/dV_j = sum_i C_gd,ij dx_i
+        for (int j = lane; j < g; j += G) {
+            const double vj = V[p * g + j];
+            double gv = 0.0;
 #pragma unroll
-        for (int r = 0; r < KG; ++r) {
-            const int j = lane + G * r;
-            if (j < g) {
-                const double vj = V[p * g + j];
-                double gv = 0.0;
-#pragma unroll
-                for (int i = 0; i < NM; ++i) {
-                    colG[r][i] += dx[i] * vj;
-                    gv += sCgd[i * kMaxGate + j] * dx[i];
-                }
-                if (gradV) gradV[p * g + j] = gv;
+            for (int i = 0; i < NM; ++i) {
+                if (i < n) atomicAdd(&sdG[i * kMaxGate + j], dx[i] * vj);
+                gv += sCgd[i * kMaxGate + j] * dx[i];
             }
-        }
-    }
-    if (lane < n) {
-#pragma unroll
-        for (int j = 0; j < NM; ++j)
-            if (j < n && rowA[j] != 0.0) atomicAdd(&sdA[lane * kMaxDot + j], rowA[j]);
-    }
-#pragma unroll
-    for (int r = 0; r < KG; ++r) {
-        const int j = lane + G * r;
-        if (j < g) {
-#pragma unroll
-            for (int i = 0; i < NM; ++i)
-                if (i < n && colG[r][i] != 0.0) atomicAdd(&sdG[i * kMaxGate + j], colG[r][i]);
+            if (gradV) gradV[p * g + j] = gv;
         }
     }
     __syncthreads();
@@ -704,21 +818,25 @@ __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restric
                                                         double *__restrict__ grad_cdd,
                                                         double *__restrict__ grad_cgd)
 {
+    __shared__ double F[1 << kBwdMaxDot];
     __shared__ double dA[kMaxDot * kMaxDot];
     __shared__ double T[kMaxDot * kMaxDot];
     const int n = dr->n, g = dr->g;
     const int tid = threadIdx.x;
+    const int ns = 1 << n;
+    for (int s = tid; s < ns; s += blockDim.x) F[s] = accU[s];
+    __syncthreads();
+    // superset sums F(T) = sum_{s contains T} u_s, one dot per pass
+    for (int b = 0; b < n; ++b) {
+        for (int s = tid; s < ns; s += blockDim.x)
+            if (!(s >> b & 1)) F[s] += F[s | (1 << b)];
+        __syncthreads();
+    }
     for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) {
         const int i = e / kMaxDot, j = e % kMaxDot;
         double v = accA[e];
-        if (i < n && j < n) {
-            // 1/2 sum_s u_s [i in s][j in s]
-            const uint32_t need = (1u << i) | (1u << j);
-            double q = 0.0;
-            for (uint32_t s = 0; s < (1u << n); ++s)
-                if ((s & need) == need) q += accU[s];
-            v += 0.5 * q;
-        }
+        // 1/2 sum_s u_s [i in s][j in s]
+        if (i < n && j < n) v += 0.5 * F[(1 << i) | (1 << j)];
         dA[e] = v;
     }
     __syncthreads();
@@ -745,18 +863,15 @@ hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P, const 
                            const SavedRec *saved, double *accA, double *accG, double *accU,
                            double *gradV, int n_dot, hipStream_t s)
 {
-    // accumulators: kMaxDot^2 + kMaxDot*kMaxGate + 2^n doubles, contiguous
-    const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + (1 << n_dot);
-    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((nacc + 255) / 256)), dim3(256), 0, s, accA,
-                       nacc);
+    // accA, accG, accU: zeroed by the caller's prologue launch
     if (n_dot <= 8) {
-        QA_DISPATCH_GROUP(n_dot, hipLaunchKernelGGL((k_soft_bwd<LG_, NM_>),
-                                                    dim3(group_blocks(P, LG_, 2048)), dim3(256), 0,
-                                                    s, dr, V, P, gbar, saved, accA, accG, accU,
-                                                    gradV));
+        QA_DISPATCH_TAB(n_dot, hipLaunchKernelGGL((k_soft_bwd<LG_, NM_, CPL_>),
+                                                  dim3(group_blocks(P, LG_, 2048)), dim3(256), 0,
+                                                  s, dr, V, P, gbar, saved, accA, accG, accU,
+                                                  gradV));
     } else {
-        hipLaunchKernelGGL((k_soft_bwd<6, 16>), dim3(group_blocks(P, 6, 2048)), dim3(256), 0, s,
-                           dr, V, P, gbar, saved, accA, accG, accU, gradV);
+        hipLaunchKernelGGL((k_soft_bwd<6, 16, 0>), dim3(group_blocks(P, 6, 2048)), dim3(256), 0,
+                           s, dr, V, P, gbar, saved, accA, accG, accU, gradV);
     }
     return hipGetLastError();
 }

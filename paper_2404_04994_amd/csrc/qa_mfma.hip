@@ -422,27 +422,39 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
     }
 }
 
-// blocks of 256 threads of the given scorer form that fit on the device at once
-static int resident_blocks(int prec)
+// blocks of 256 threads of a scorer kernel that fit on the device at once
+// (cached per kernel slot and device; 0 if unknown)
+template <typename Kernel>
+static int resident_blocks(Kernel kernel, int slot)
 {
-    static int cache[4][64];  // [prec][device] (0 = not yet known)
+    static int cache[8][64];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || prec < 1 || prec > 3) return 0;
-    int &c = cache[prec][dev];
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || slot < 0 || slot >= 8) return 0;
+    int &c = cache[slot][dev];
     if (c) return c;
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    hipError_t e = hipErrorInvalidValue;
-    if (prec == kPrecFP32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_mfma<kPrecFP32>, 256, 0);
-    else if (prec == kPrecX3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_mfma<kPrecX3>, 256, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_score_mfma<kPrecX2>, 256, 0);
-    if (e != hipSuccess || per_cu <= 0) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        per_cu <= 0)
+        return 0;
     c = cus * per_cu;
     return c;
+}
+
+template <typename Kernel>
+static hipError_t launch_persistent(Kernel kernel, int slot, const DiagRec *dr, const PixRec *pr,
+                                    int64_t P, int32_t *n_out, int32_t *flag_list,
+                                    int64_t *counters, hipStream_t s)
+{
+    // persistent waves: as many blocks as the chip keeps resident, at most
+    // one wave per pixel
+    int64_t blocks = (P + 3) / 4;
+    const int resident = resident_blocks(kernel, slot);
+    if (resident > 0 && blocks > resident) blocks = resident;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, s, dr, pr, P, n_out,
+                       flag_list, counters);
+    return hipGetLastError();
 }
 
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
@@ -451,29 +463,19 @@ hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int
 {
     if (n_dot < 9 || n_dot > 16) return hipErrorInvalidValue;
     if (P <= 0) return hipSuccess;
-    // persistent waves: as many blocks as the chip keeps resident, at most
-    // one wave per pixel
-    int64_t blocks = (P + 3) / 4;
-    const int resident = resident_blocks(prec);
-    if (resident > 0 && blocks > resident) blocks = resident;
-    const dim3 grid((unsigned)blocks), block(256);
     switch (prec) {
     case kPrecFP32:
-        hipLaunchKernelGGL(k_score_mfma<kPrecFP32>, grid, block, 0, s, dr, pr, P, n_out,
-                           flag_list, counters);
-        break;
+        return launch_persistent(k_score_mfma<kPrecFP32>, 0, dr, pr, P, n_out, flag_list,
+                                 counters, s);
     case kPrecX3:
-        hipLaunchKernelGGL(k_score_mfma<kPrecX3>, grid, block, 0, s, dr, pr, P, n_out, flag_list,
-                           counters);
-        break;
+        return launch_persistent(k_score_mfma<kPrecX3>, 1, dr, pr, P, n_out, flag_list, counters,
+                                 s);
     case kPrecX2:
-        hipLaunchKernelGGL(k_score_mfma<kPrecX2>, grid, block, 0, s, dr, pr, P, n_out, flag_list,
-                           counters);
-        break;
+        return launch_persistent(k_score_mfma<kPrecX2>, 2, dr, pr, P, n_out, flag_list, counters,
+                                 s);
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace qa
