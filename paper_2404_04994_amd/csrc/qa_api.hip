@@ -52,6 +52,9 @@ struct Workspace {
     int64_t pr_cap = 0;
     int32_t *flag_list = nullptr;
     int64_t flag_cap = 0;
+    int32_t *bstats = nullptr;          // per-block counts of the setup kernel
+    int64_t bstats_cap = 0;
+    int64_t bstats_used = 0;            // blocks of the last single-diagram setup
     int64_t *counters = nullptr;
     double *acc = nullptr;
     int64_t acc_cap = 0;
@@ -145,7 +148,7 @@ qa_status get_ws(hipStream_t stream, Workspace **out)
     if (it == g_ws.end()) {
         Workspace *w = new Workspace();
         w->stream = stream;
-        if (hipMalloc((void **)&w->counters, sizeof(int64_t) * C_NUM) != hipSuccess) {
+        if (hipMalloc((void **)&w->counters, sizeof(int64_t) * kCounterWords) != hipSuccess) {
             delete w;
             return fail(QA_E_WORKSPACE, "hipMalloc of the counters failed");
         }
@@ -260,6 +263,8 @@ qa_status grow_single(Workspace *w, int64_t P)
     if (w->dr != dr0) w->dr_inputs.clear();
     if ((st = grow(w, w->pr, w->pr_cap, P))) return st;
     if ((st = grow(w, w->flag_list, w->flag_cap, P))) return st;
+    // four counts per setup block; N = 16 has the most blocks
+    if ((st = grow(w, w->bstats, w->bstats_cap, 4 * setup_blocks(P, kMaxDot)))) return st;
     return QA_OK;
 }
 
@@ -270,16 +275,15 @@ bool use_matrix_cores(const qa_problem *pb)
 }
 
 // The device work of one single-diagram call on stream s (inputs already in
-// w->dr): counters, prologue, setup, QP, then either the T = 0 scoring
-// (n_out) or the softargmin (nbar, saved).  ev: optional stage events.
+// w->dr): prologue, setup and QP in one kernel, then either the T = 0
+// scoring (n_out) or the softargmin (nbar, saved).  ev: optional stage events.
 qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, const double *V,
                          int64_t P, int32_t *n_out, double *nbar, SavedRec *saved,
                          std::array<hipEvent_t, 4> *ev)
 {
     const bool closed = pb->mode == QA_CLOSED;
     if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
-    QA_HIP(launch_prep(w->dr, 1, w->counters, s));
-    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->counters, pb->n_dot, closed, s));
+    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->counters, w->bstats, pb->n_dot, closed, s));
     if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
     if (nbar) {
         QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
@@ -307,6 +311,7 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
     qa_status st;
     if ((st = grow_single(w, P))) return st;
     if ((st = upload_diag(w, pb))) return st;
+    w->bstats_used = setup_blocks(P, pb->n_dot);
     std::array<hipEvent_t, 4> *ev = timing_slot(w);
     if (ev || !g_graphs) return enqueue_single(w, w->stream, pb, V, P, n_out, nbar, saved, ev);
     const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + pb->precision : 1);
@@ -314,7 +319,8 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
                                 (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
                                 (int64_t)(uintptr_t)saved, (int64_t)(uintptr_t)w->dr,
                                 (int64_t)(uintptr_t)w->pr,
-                                (int64_t)(uintptr_t)w->flag_list};
+                                (int64_t)(uintptr_t)w->flag_list,
+                                (int64_t)(uintptr_t)w->bstats};
     auto it = w->graphs.find(key);
     if (it == w->graphs.end()) {
         if (w->graphs.size() >= 16) {
@@ -344,9 +350,22 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
 qa_status read_stats(Workspace *w, qa_stats *stats)
 {
     if (!stats) return QA_OK;
-    int64_t c[C_NUM];
-    QA_HIP(hipMemcpyAsync(c, w->counters, sizeof c, hipMemcpyDeviceToHost, w->stream));
+    std::vector<int64_t> all(kCounterWords);
+    QA_HIP(hipMemcpyAsync(all.data(), w->counters, sizeof(int64_t) * kCounterWords,
+                          hipMemcpyDeviceToHost, w->stream));
     QA_HIP(hipStreamSynchronize(w->stream));
+    std::vector<int32_t> blk(4 * w->bstats_used);
+    if (w->bstats_used)
+        QA_HIP(hipMemcpyAsync(blk.data(), w->bstats, sizeof(int32_t) * blk.size(),
+                              hipMemcpyDeviceToHost, w->stream));
+    QA_HIP(hipStreamSynchronize(w->stream));
+    int64_t c[C_NUM] = {};
+    for (int slot = 0; slot < kCounterSlots; ++slot)
+        for (int i = 0; i < C_NUM; ++i) c[i] += all[slot * C_NUM + i];
+    // counts of the single-diagram setup kernel, per block
+    const int which[4] = {C_PIXELS, C_QP, C_DOUBLED, C_QP_FAIL};
+    for (int64_t b = 0; b < w->bstats_used; ++b)
+        for (int k = 0; k < 4; ++k) c[which[k]] += blk[4 * b + k];
     stats->pixels = c[C_PIXELS];
     stats->qp_pixels = c[C_QP];
     stats->qp_failures = c[C_QP_FAIL];
@@ -397,9 +416,9 @@ qa_status qa_continuous_min(const qa_problem *prob, const double *V_dev, int64_t
     if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
     if ((st = grow_single(w, P))) return st;
     if ((st = upload_diag(w, prob))) return st;
-    QA_HIP(launch_prep(w->dr, 1, w->counters, w->stream));
-    QA_HIP(launch_setup(w->dr, V_dev, P, w->pr, w->counters, prob->n_dot,
+    QA_HIP(launch_setup(w->dr, V_dev, P, w->pr, w->counters, w->bstats, prob->n_dot,
                         prob->mode == QA_CLOSED, w->stream, x_out_dev, flags_out_dev));
+    w->bstats_used = setup_blocks(P, prob->n_dot);
     return read_stats(w, stats);
 }
 
@@ -528,7 +547,7 @@ qa_status upload_plan(Workspace *w, const BatchPlan &plan, int32_t n_diag)
 qa_status enqueue_batch(Workspace *w, hipStream_t s, int32_t n_diag, const BatchPlan &plan,
                         const double *V, int32_t *n_out, double *nbar, int blocks)
 {
-    QA_HIP(launch_zero_i64(w->counters, C_NUM, s));
+    QA_HIP(launch_zero_i64(w->counters, kCounterWords, s));
     QA_HIP(launch_prep_batch(w->bhdr, w->bmats, w->brecs, n_diag, s));
     QA_HIP(launch_batch(w->bhdr, w->brecs, n_diag, plan.tiles, V, n_out, nbar, w->counters,
                         plan.max_dot, blocks, s));
@@ -576,6 +595,7 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
         max_dot = std::max(max_dot, probs[d].n_dot);
         n_soft += probs[d].kT > 0.0;
     }
+    w->bstats_used = 0;  // the batched kernels count into the counter slots only
     std::vector<int64_t> sig = {n_diag, total, max_dot, n_soft > 0 && nbar_out_dev != nullptr};
     BatchPlan plan;
     auto it = g_tune.find(sig);
@@ -707,6 +727,7 @@ void qa_release(void *hip_stream)
     (void)hipFree(w->dr);
     (void)hipFree(w->pr);
     (void)hipFree(w->flag_list);
+    (void)hipFree(w->bstats);
     (void)hipFree(w->counters);
     (void)hipFree(w->acc);
     for (auto &e : w->ev)

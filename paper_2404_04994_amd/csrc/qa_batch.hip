@@ -23,6 +23,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_batch(const BatchHdr *__r
                                                    DiagRec *__restrict__ recs)
 {
     __shared__ double M[kMaxDot * kMaxDot];
+    __shared__ double cvec[kMaxDot];
     __shared__ double red[8];
     const BatchHdr h = hdr[blockIdx.x];
     DiagRec *dr = recs + blockIdx.x;
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_batch(const BatchHdr *__r
         dr->prec = 0;
     }
     __syncthreads();
-    prep_body(dr, M, red);
+    prep_body(dr, M, cvec, red);
 }
 
 hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *recs, int n_diag,
@@ -305,8 +306,25 @@ __global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
     __shared__ int64_t sitem;
     const int lane = threadIdx.x;
     int64_t npix = 0, nqp = 0, nfail = 0, ndbl = 0, ngap = 0, ncand = 0;
+    // The work queue is sharded over the kCounterSlots counter lines: slot s
+    // hands out items s, s + kCounterSlots, ... (each shard keeps the plan's
+    // largest-first order).  A block drains its home slot, then takes what
+    // is left in the others; a plain read skips shards already exhausted, so
+    // no single address sees every block's atomics.
+    const int home = blockIdx.x & (kCounterSlots - 1);
+    int shard = 0;
     for (;;) {
-        if (lane == 0) sitem = (int64_t)atomicAdd((unsigned long long *)&counters[C_WORK], 1ull);
+        if (lane == 0) {
+            int64_t it = tiles;
+            for (; shard < kCounterSlots; ++shard) {
+                const int sl = (home + shard) & (kCounterSlots - 1);
+                int64_t *cur = &counters[sl * C_NUM + C_WORK];
+                if ((int64_t)sl + kCounterSlots * *(volatile int64_t *)cur >= tiles) continue;
+                it = (int64_t)sl + kCounterSlots * (int64_t)atomicAdd((unsigned long long *)cur, 1ull);
+                if (it < tiles) break;
+            }
+            sitem = it;
+        }
         __syncthreads();
         const int64_t item = sitem;
         if (item >= tiles) break;

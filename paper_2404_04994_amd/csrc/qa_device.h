@@ -30,10 +30,6 @@ __device__ __forceinline__ bool better(double e, uint32_t s, double e1, uint32_t
     return e < e1 || (e == e1 && __brev(s) < __brev(s1));
 }
 
-__device__ __forceinline__ void block_add_counter(int64_t *counters, int which, int64_t v)
-{
-    if (v) atomicAdd((unsigned long long *)&counters[which], (unsigned long long)v);
-}
 
 // Candidate set of Sec. 3.2 for the continuous minimum x: base state n0,
 // mask of dots that take both roundings and, for closed arrays, the number k
@@ -302,8 +298,10 @@ __device__ __forceinline__ double group_sum(double v)
 constexpr int kPrepThreads = 256;  // one thread per element of a 16 x 16 matrix
 
 // Prologue of one diagram, run by one 256-thread block (thread t owns element
-// (t / 16, t % 16)): A = C_dd^{-1} (FP64), C_dd 1, 1^T C_dd 1, sum|A|/2 and the
-// pixel-independent energy tables.  M is 256 doubles of LDS, red 8 doubles.
+// (t / 16, t % 16)).  prep_inverse leaves in LDS the symmetric A = C_dd^{-1}
+// (M, 256 doubles), C_dd 1 (cvec, 16 doubles), 1^T C_dd 1 (red[4]) and
+// sum|A|/2 (red[5]); prep_store writes them and the pixel-independent energy
+// tables to the diagram record.
 //
 // The inverse is an in-place Gauss-Jordan elimination of the positive
 // definite C_dd without pivoting (every pivot is a diagonal entry of a
@@ -311,7 +309,7 @@ constexpr int kPrepThreads = 256;  // one thread per element of a 16 x 16 matrix
 // has checked definiteness by Cholesky).  Pivot k maps
 //   m_kk -> 1/p,  m_kj -> m_kj/p,  m_ik -> -m_ik/p,  m_ij -> m_ij - m_ik m_kj/p,
 // and after the n pivots M = C_dd^{-1}.  Dots beyond n stay identity rows.
-__device__ inline void prep_body(DiagRec *dr, double *M, double *red)
+__device__ inline void prep_inverse(const DiagRec *dr, double *M, double *cvec, double *red)
 {
     const int n = dr->n;
     const int tid = threadIdx.x;
@@ -336,7 +334,6 @@ __device__ inline void prep_body(DiagRec *dr, double *M, double *red)
     const double a = (i < n && j < n) ? 0.5 * (m + M[j * kMaxDot + i]) : 0.0;
     __syncthreads();
     M[tid] = a;
-    dr->A[tid] = a;
     // sum |A_ij| / 2: wave sums, then the four partial sums
     double sa = fabs(a);
 #pragma unroll
@@ -347,16 +344,27 @@ __device__ inline void prep_body(DiagRec *dr, double *M, double *red)
         double c = 0.0;
         if (tid < n)
             for (int q = 0; q < n; ++q) c += dr->Cdd[tid * kMaxDot + q];
-        dr->c[tid] = c;
+        cvec[tid] = c;
         double oc = c;
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) oc += __shfl_xor(oc, off, 16);
         if (tid == 0) red[4] = oc;
     }
     __syncthreads();
+    if (tid == 0) red[5] = 0.5 * (red[0] + red[1] + red[2] + red[3]);
+    __syncthreads();
+}
+
+__device__ inline void prep_store(DiagRec *dr, const double *M, const double *cvec,
+                                  const double *red)
+{
+    const int n = dr->n;
+    const int tid = threadIdx.x;
+    dr->A[tid] = M[tid];
+    if (tid < kMaxDot) dr->c[tid] = cvec[tid];
     if (tid == 0) {
         dr->one_c = red[4];
-        dr->sumabs = (float)(0.5 * (red[0] + red[1] + red[2] + red[3]));
+        dr->sumabs = (float)red[5];
     }
     // tables of the matrix-core scorer: low part = dots 0..7, high = 8..n-1
     if (n >= 9) {
@@ -396,6 +404,12 @@ __device__ inline void prep_body(DiagRec *dr, double *M, double *red)
         }
         dr->hs[tid] = 0.5 * h;
     }
+}
+
+__device__ inline void prep_body(DiagRec *dr, double *M, double *cvec, double *red)
+{
+    prep_inverse(dr, M, cvec, red);
+    prep_store(dr, M, cvec, red);
 }
 
 }  // namespace qa

@@ -21,7 +21,13 @@ constexpr int kMaxDot = 16;
 constexpr int kMaxGate = 32;
 constexpr int kWave = 64;
 
-// counters (int64) kept in the workspace, mirrored into qa_stats
+// counters (int64) kept in the workspace, mirrored into qa_stats.  Atomics
+// on one address from every block serialise at the memory side, so the
+// statistics are spread over kCounterSlots cache lines ([slot][C_NUM], a
+// block adds to slot blockIdx mod kCounterSlots) and summed by the host.
+// C_FLAG_LIST is a list cursor in slot 0 only; C_WORK is the cursor of one
+// shard of the batched kernel's work queue in every slot.
+constexpr int kCounterSlots = 64;
 enum Counter {
     C_PIXELS = 0,
     C_QP = 1,
@@ -33,9 +39,18 @@ enum Counter {
     C_UNUSED7 = 7,
     C_FLAG_LIST = 8,    // length of the full FP64 re-score list
     C_BAND_OVERFLOW = 9,
-    C_WORK = 10,        // work-queue cursor of the batched kernel
+    C_WORK = 10,        // work-queue shard cursor of the batched kernel
     C_NUM = 16
 };
+constexpr int kCounterWords = kCounterSlots * C_NUM;
+
+// add a block's partial count to its counter slot
+__device__ __forceinline__ void block_add_counter(int64_t *counters, int which, int64_t v)
+{
+    if (v)
+        atomicAdd((unsigned long long *)&counters[(blockIdx.x & (kCounterSlots - 1)) * C_NUM + which],
+                  (unsigned long long)v);
+}
 
 struct alignas(16) DiagRec {
     // inputs (written by the host, or by k_prep_batch): everything up to Cgd
@@ -97,13 +112,18 @@ struct alignas(8) BatchHdr {
 // error of the launch.
 // -------------------------------------------------------------------------
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s);
-// prologue of n_diag diagrams; also zeroes the C_NUM counters and the nzero
-// doubles at zero when given
+// prologue of n_diag diagrams; also zeroes the kCounterWords counters and
+// the nzero doubles at zero when given
 hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s,
                        double *zero = nullptr, int64_t nzero = 0);
-// setup of every pixel; x_out (P x N) / flags_out (P) optional copies of x*
-hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                        int64_t *counters, int n_dot, bool closed, hipStream_t s,
+// prologue (every block; block 0 also stores A and the tables into dr and
+// clears the kCounterWords counters) and setup of every pixel; the per-block
+// counts {pixels, QP, doubled, QP failures} go to bstats[4 * block] for
+// setup_blocks(P, n_dot) blocks; x_out (P x N) / flags_out (P) are optional
+// copies of x*.  P >= 1.
+int64_t setup_blocks(int64_t P, int n_dot);
+hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int64_t *counters,
+                        int32_t *bstats, int n_dot, bool closed, hipStream_t s,
                         double *x_out = nullptr, int32_t *flags_out = nullptr);
 // T = 0 argmin in FP64 over the listed pixels (list == nullptr: all P)
 hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P,

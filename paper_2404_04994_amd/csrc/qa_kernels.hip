@@ -37,13 +37,15 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(DiagRec *dr_all, int64_t 
                                                       double *zero, int64_t nzero)
 {
     __shared__ double M[kMaxDot * kMaxDot];
+    __shared__ double cvec[kMaxDot];
     __shared__ double red[8];
     // the call's counters (and accumulators) start at zero: no separate
     // memset or fill kernel in the launch sequence
-    if (counters && blockIdx.x == 0 && threadIdx.x < C_NUM) counters[threadIdx.x] = 0;
+    if (counters && blockIdx.x == 0)
+        for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0;
     if (zero && blockIdx.x == 0)
         for (int64_t i = threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0.0;
-    prep_body(dr_all + blockIdx.x, M, red);
+    prep_body(dr_all + blockIdx.x, M, cvec, red);
 }
 
 hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s, double *zero,
@@ -137,35 +139,44 @@ __device__ __forceinline__ void gj_pivot(double (&r)[NM], double &v, int k, int 
 }
 
 template <int NM, bool CLOSED>
-__global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
+__global__ __launch_bounds__(256) void k_setup(DiagRec *__restrict__ dr,
                                                const double *__restrict__ V, int64_t P,
                                                PixRec *__restrict__ pr,
                                                int64_t *__restrict__ counters,
+                                               int32_t *__restrict__ bstats,
                                                double *__restrict__ x_out,
                                                int32_t *__restrict__ flags_out)
 {
+    __shared__ double sA[kMaxDot * kMaxDot];  // A (symmetric), from the prologue
+    __shared__ double sc[kMaxDot];            // C_dd 1
+    __shared__ double red[8];
     __shared__ double sK[NM * NM];         // K (symmetric), identity beyond n
-    __shared__ double sA[NM * NM];         // A (symmetric)
     __shared__ double sG[kMaxGate * NM];   // C_gd transposed: sG[j * NM + i]
-    __shared__ double sc[NM];              // C_dd 1
-    __shared__ unsigned long long cnt[4];
+    __shared__ int cnt[4];
+    // the diagram prologue, in every block (a few microseconds of latency,
+    // no separate launch); block 0 also publishes A and the energy tables
+    // for the scoring kernels and clears the call's counters
+    prep_inverse(dr, sA, sc, red);
+    if (blockIdx.x == 0) {
+        prep_store(dr, sA, sc, red);
+        if (counters)
+            for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0;
+    }
     const int n = dr->n, g = dr->g;
-    const double one_c = dr->one_c;
+    const double one_c = red[4];
     for (int e = threadIdx.x; e < NM * NM; e += blockDim.x) {
         const int i = e / NM, j = e % NM;
         double kv = (i == j) ? 1.0 : 0.0;
         if (i < n && j < n) {
             kv = dr->Cdd[i * kMaxDot + j];
-            if (CLOSED) kv -= dr->c[i] * dr->c[j] / one_c;
+            if (CLOSED) kv -= sc[i] * sc[j] / one_c;
         }
         sK[e] = kv;
-        sA[e] = dr->A[i * kMaxDot + j];
     }
     for (int e = threadIdx.x; e < kMaxGate * NM; e += blockDim.x) {
         const int j = e / NM, i = e % NM;
         sG[e] = dr->Cgd[i * kMaxGate + j];
     }
-    if (threadIdx.x < NM) sc[threadIdx.x] = dr->c[threadIdx.x];
     if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
     __syncthreads();
 
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
     const double z = is_dot ? (double)n0 - xu : 0.0;
     double g0 = 0.0;
 #pragma unroll
-    for (int q = 0; q < NM; ++q) g0 += sA[q * NM + dot] * __shfl(z, base + q, kWave);
+    for (int q = 0; q < NM; ++q) g0 += sA[q * kMaxDot + dot] * __shfl(z, base + q, kWave);
     const double u0 = 0.5 * group_dsum<NM>(z * g0);
 
     if (p < P) {
@@ -266,20 +277,17 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
             o->flags = flags | cflags;
             o->pad = 0;
             if (flags_out) flags_out[p] = flags | (cflags & 4);
-            if (cflags & 4) atomicAdd(&cnt[2], 1ull);
-            if (flags & 1) atomicAdd(&cnt[1], 1ull);
-            if (flags & 2) atomicAdd(&cnt[3], 1ull);
-            atomicAdd(&cnt[0], 1ull);
+            if (cflags & 4) atomicAdd(&cnt[2], 1);
+            if (flags & 1) atomicAdd(&cnt[1], 1);
+            if (flags & 2) atomicAdd(&cnt[3], 1);
+            atomicAdd(&cnt[0], 1);
         }
         if (x_out && is_dot) x_out[p * n + dot] = x;
     }
+    // per-block counts with plain stores (the host sums them): the counters
+    // of this call are cleared by block 0 concurrently, so no atomics here
     __syncthreads();
-    if (threadIdx.x == 0) {
-        block_add_counter(counters, C_PIXELS, cnt[0]);
-        block_add_counter(counters, C_QP, cnt[1]);
-        block_add_counter(counters, C_DOUBLED, cnt[2]);
-        block_add_counter(counters, C_QP_FAIL, cnt[3]);
-    }
+    if (threadIdx.x < 4) bstats[blockIdx.x * 4 + threadIdx.x] = cnt[threadIdx.x];
 }
 
 #define QA_DISPATCH_NM(n, CALL)                        \
@@ -290,20 +298,24 @@ __global__ __launch_bounds__(256) void k_setup(const DiagRec *__restrict__ dr,
         else { constexpr int NM_ = 16; CALL; }         \
     } while (0)
 
-hipError_t launch_setup(const DiagRec *dr, const double *V, int64_t P, PixRec *pr,
-                        int64_t *counters, int n_dot, bool closed, hipStream_t s,
-                        double *x_out, int32_t *flags_out)
+int64_t setup_blocks(int64_t P, int n_dot)
 {
-    if (P <= 0) return hipSuccess;
-    const dim3 block(256);
+    int64_t b = 0;
+    QA_DISPATCH_NM(n_dot, b = (P * NM_ + 255) / 256);
+    return b < 1 ? 1 : b;
+}
+
+hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int64_t *counters,
+                        int32_t *bstats, int n_dot, bool closed, hipStream_t s, double *x_out,
+                        int32_t *flags_out)
+{
+    const dim3 grid((unsigned)setup_blocks(P, n_dot)), block(256);
     if (closed)
-        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>),
-                                                 dim3((unsigned)((P * NM_ + 255) / 256)), block, 0,
-                                                 s, dr, V, P, pr, counters, x_out, flags_out));
+        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>), grid, block, 0, s, dr, V,
+                                                 P, pr, counters, bstats, x_out, flags_out));
     else
-        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, false>),
-                                                 dim3((unsigned)((P * NM_ + 255) / 256)), block, 0,
-                                                 s, dr, V, P, pr, counters, x_out, flags_out));
+        QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, false>), grid, block, 0, s, dr, V,
+                                                 P, pr, counters, bstats, x_out, flags_out));
     return hipGetLastError();
 }
 

@@ -61,8 +61,12 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi)
 constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
 constexpr int kMaxBand = 256;  // near-tie states re-scored in FP64 inside the kernel
 
+#ifndef QA_SCORER_WAVES
+#define QA_SCORER_WAVES 3
+#endif
+
 template <int PREC>
-__global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ dr,
+__global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagRec *__restrict__ dr,
                                                     const PixRec *__restrict__ pr, int64_t P,
                                                     int32_t *__restrict__ n_out,
                                                     int32_t *__restrict__ flag_list,
@@ -76,6 +80,7 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
     __shared__ int sbandn[4];
     __shared__ double sG64[4][kMaxDot];
     __shared__ uint2 sCt[4][256];  // per wave: BF16 parts of C(c_hi) of its pixel
+    __shared__ float sGm[4][16][64];  // per wave: lane minima of each row tile
     __shared__ unsigned long long sflag, sover, sgap;
     for (int e = threadIdx.x; e < 128; e += blockDim.x) {
         sT1[e / 8][e % 8] = dr->T1[e / 8][e % 8];
@@ -126,12 +131,15 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
         }
     }
 
-    // Persistent waves: wave w scores pixels w, w + nwaves, ...  Lane i < 16
-    // holds g0_i and n0_i of its pixel (vector loads, one pixel ahead).
+    // Persistent waves: wave w scores pixels w, w + nwaves, ... (a static
+    // interleave: a shared work-queue cursor costs more in same-address
+    // atomics than it recovers in balance).  Lane i < 16 holds g0_i and n0_i
+    // of its pixel (vector loads, one pixel ahead).
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     int64_t nflag = 0, nover = 0, ngap = 0;
     const int li = lane & 15;
+    float *gmrec = &sGm[threadIdx.x >> 6][0][0];
     double gnext = 0.0;
     int nnext = 0;
     if (wave < P) {
@@ -268,13 +276,22 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
             Pack8 a;
             float af[3];
             build_a(rt, a, af);
-            float gm = INFINITY;
+            // software-pipelined: the minima of tile ct - 1 are taken while
+            // tile ct is on the matrix core (two independent minimum chains)
+            float gm = INFINITY, gm2 = INFINITY;
+            f32x4_t dp = tile(a, af, 0);
 #pragma unroll
-            for (int ct = 0; ct < 16; ++ct) {
+            for (int ct = 1; ct < 16; ++ct) {
                 const f32x4_t d = tile(a, af, ct);
-                gm = fminf(fminf(gm, d[0]), d[1]);
-                gm = fminf(fminf(gm, d[2]), d[3]);
+                float &m = (ct & 1) ? gm : gm2;
+                m = fminf(fminf(m, dp[0]), dp[1]);
+                m = fminf(fminf(m, dp[2]), dp[3]);
+                dp = d;
             }
+            gm2 = fminf(fminf(gm2, dp[0]), dp[1]);
+            gm2 = fminf(fminf(gm2, dp[2]), dp[3]);
+            gm = fminf(gm, gm2);
+            gmrec[rt * 64 + lane] = gm;
             if (gm < best1) { best2 = best1; best1 = gm; rt1 = rt; }
             else best2 = fminf(best2, gm);
         }
@@ -339,6 +356,8 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
         if (lane == 0) *bandn = 0;
         __builtin_amdgcn_wave_barrier();
         for (int rt = 0; rt < nrt; ++rt) {
+            // row tiles whose lane minima all lie above the band hold none of it
+            if (!__ballot(gmrec[rt * 64 + lane] <= thr)) continue;
             Pack8 a;
             float af[3];
             build_a(rt, a, af);
@@ -412,13 +431,11 @@ __global__ __launch_bounds__(256) void k_score_mfma(const DiagRec *__restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (sflag) atomicAdd((unsigned long long *)&counters[C_NEAR_TIE], sflag);
-        if (sover) atomicAdd((unsigned long long *)&counters[C_BAND_OVERFLOW], sover);
-        if (sgap) atomicAdd((unsigned long long *)&counters[C_GAP_1E9], sgap);
+        block_add_counter(counters, C_NEAR_TIE, (int64_t)sflag);
+        block_add_counter(counters, C_BAND_OVERFLOW, (int64_t)sover);
+        block_add_counter(counters, C_GAP_1E9, (int64_t)sgap);
         // every pixel scores all 2^n candidates of its box on the matrix cores
-        if (blockIdx.x == 0)
-            atomicAdd((unsigned long long *)&counters[C_CANDIDATES],
-                      (unsigned long long)P << n);
+        if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
     }
 }
 
