@@ -305,27 +305,46 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) other = fminf(other, __shfl_xor(other, off));
         const int rtw = __shfl(rt1, winner);
-        // ---- recompute the winning row tile: index and in-group runner-up ----
-        float v1 = INFINITY, v2 = INFINITY;
-        int i1 = 0;
+        // ---- recompute the winning row tile: per lane the two smallest tile
+        // minima and the tile of the smallest; then the winner's tile once
+        // more for the index and the runner-up inside it ----
+        float e1, e2;
+        int iw;
         {
             Pack8 a;
             float af[3];
             build_a(rtw, a, af);
+            float t1 = INFINITY, t2 = INFINITY;
+            int ct1 = 0;
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct) {
                 const f32x4_t d = tile(a, af, ct);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float e = d[i];
-                    if (e < v1) { v2 = v1; v1 = e; i1 = ct * 4 + i; }
-                    else v2 = fminf(v2, e);
-                }
+                const float tm = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
+                const bool lt = tm < t1;
+                t2 = lt ? t1 : fminf(t2, tm);
+                t1 = lt ? tm : t1;
+                ct1 = lt ? ct : ct1;
             }
+            // the winner lane's tile: a scalar (readfirstlane) choice among
+            // static indices, so the branch is taken by the whole wave (a
+            // matrix-core instruction ignores the lane mask)
+            const int ctw = __builtin_amdgcn_readfirstlane(__shfl(ct1, winner));
+            const float t2w = __shfl(t2, winner);
+            f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ct = 0; ct < 16; ++ct)
+                if (ct == ctw) d = tile(a, af, ct);
+            float v1 = d[0], v2 = INFINITY;
+            int i1 = 0;
+#pragma unroll
+            for (int i = 1; i < 4; ++i) {
+                if (d[i] < v1) { v2 = v1; v1 = d[i]; i1 = i; }
+                else v2 = fminf(v2, d[i]);
+            }
+            e1 = __shfl(v1, winner);
+            iw = ctw * 4 + __shfl(i1, winner);
+            e2 = fminf(other, fminf(t2w, __shfl(v2, winner)));
         }
-        const float e1 = __shfl(v1, winner);
-        const int iw = __shfl(i1, winner);
-        const float e2 = fminf(other, __shfl(v2, winner));
         // Certified bound on |E_approx - E| for every candidate of the pixel.
         // All inputs of the tile sum are bounded by S = sum|g| + 1/2 sum|A|
         // (g' parts, C parts and h parts together), FP32 rounding of the
