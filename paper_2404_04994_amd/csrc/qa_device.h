@@ -379,6 +379,8 @@ __device__ inline void prep_store(DiagRec *dr, const double *M, const double *cv
             }
             dr->T1[r][q] = (float)t1;
             dr->T2[r][q] = (float)t2;
+            dr->T1d[r][q] = t1;
+            dr->T2d[r][q] = t2;
         }
         double hh = 0.0, hl = 0.0;
 #pragma unroll
@@ -392,6 +394,8 @@ __device__ inline void prep_store(DiagRec *dr, const double *M, const double *cv
             }
         dr->hlo[tid] = (float)(0.5 * hl);
         dr->Hhi[tid] = (tid < (1 << nh)) ? (float)(0.5 * hh) : 1e30f;
+        dr->hlod[tid] = 0.5 * hl;
+        dr->Hhid[tid] = (tid < (1 << nh)) ? 0.5 * hh : 1e300;
     } else {
         // whole-box table of the lane walk: h(s) = 1/2 s^T A s, s < 2^n
         double h = 0.0;

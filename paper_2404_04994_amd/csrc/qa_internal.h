@@ -72,6 +72,9 @@ struct alignas(16) DiagRec {
     float sumabs;                 // sum |A_ij| / 2, bound used by the error band
     float pad1[3];
     double hs[256];               // n <= 8: 1/2 s^T A s for every s in {0,1}^n
+    // FP64 copies of the matrix-core tables (the near-tie re-score)
+    double T1d[16][8], T2d[16][8];
+    double Hhid[256], hlod[256];
 };
 
 // bytes of a DiagRec the host uploads (the inputs)

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     __shared__ float sT1[16][8];
     __shared__ float sT2[16][8];
     __shared__ float sH[256];
-    __shared__ double sA64[kMaxDot * kMaxDot];
+    __shared__ double sT1d[16][8], sT2d[16][8];  // FP64 tables of the near-tie re-score
+    __shared__ double sHd[256], sLd[256];
     __shared__ int sband[4][kMaxBand];
     __shared__ int sbandn[4];
     __shared__ double sG64[4][kMaxDot];
@@ -88,7 +89,12 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     }
     for (int e = threadIdx.x; e < 256; e += blockDim.x) {
         sH[e] = dr->Hhi[e];
-        sA64[e] = dr->A[e];
+        sHd[e] = dr->Hhid[e];
+        sLd[e] = dr->hlod[e];
+        if (e < 128) {
+            sT1d[e / 8][e % 8] = dr->T1d[e / 8][e % 8];
+            sT2d[e / 8][e % 8] = dr->T2d[e / 8][e % 8];
+        }
     }
     if (threadIdx.x == 0) { sflag = 0; sover = 0; sgap = 0; }
     __syncthreads();
@@ -414,17 +420,16 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
         uint32_t c1 = 0;
         for (int j = lane; j < cnt; j += 64) {
             const uint32_t c = (uint32_t)band[j];
-            // U(n0 + b) - U(n0) = sum_i b_i (g_i + 1/2 sum_k b_k A_ik)
-            double e = 0.0;
-#pragma unroll 1
-            for (int i = 0; i < n; ++i) {
-                if (c >> i & 1u) {
-                    double s = g64[i];
-#pragma unroll 4
-                    for (int k = 0; k < kMaxDot; ++k)
-                        if (c >> k & 1u) s += 0.5 * sA64[i * kMaxDot + k];
-                    e += s;
-                }
+            // the same split in FP64:
+            // U(n0 + b) - U(n0) = b_lo^T (g_lo + A_LH b_hi) + h_lo(c_lo)
+            //                   + b_hi^T g_hi + 1/2 b_hi^T A_HH b_hi
+            const uint32_t clo = c & 255u, chi = c >> 8;
+            const int row = chi & 15, rt = chi >> 4;
+            double e = sLd[clo] + sHd[chi];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (chi >> i & 1u) e += g64[8 + i];
+                if (clo >> i & 1u) e += (g64[i] + sT1d[row][i]) + sT2d[rt][i];
             }
             if (e < b1 || (e == b1 && __brev(c) < __brev(c1))) { b2 = b1; b1 = e; c1 = c; }
             else b2 = fmin(b2, e);
