@@ -313,23 +313,42 @@ __device__ inline void prep_inverse(const DiagRec *dr, double *M, double *cvec, 
 {
     const int n = dr->n;
     const int tid = threadIdx.x;
-    const int i = tid >> 4, j = tid & 15;
-    const double cij = dr->Cdd[tid];
-    double m = (i < n && j < n) ? cij : (i == j ? 1.0 : 0.0);
-    M[tid] = m;
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double piv = M[k * kMaxDot + k];
-        const double mik = M[i * kMaxDot + k], mkj = M[k * kMaxDot + j];
-        __syncthreads();
-        const double r = 1.0 / piv;
-        if (i == k && j == k) m = r;
-        else if (i == k) m = mkj * r;
-        else if (j == k) m = -mik * r;
-        else m = m - mik * mkj * r;
-        M[tid] = m;
-        __syncthreads();
+    if (tid < kWave) {
+        // wave 0 eliminates in registers: lane l holds row l / 4, columns
+        // 4 (l % 4) .. 4 (l % 4) + 3; the pivot row, the pivot column and the
+        // pivot come from the owning lanes by shuffles (no barriers)
+        const int i = tid >> 2, j0 = 4 * (tid & 3);
+        double m[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = j0 + q;
+            m[q] = (i < n && j < n) ? dr->Cdd[i * kMaxDot + j] : (i == j ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxDot; ++k) {
+            if (k < n) {
+                const double mik = __shfl(m[k & 3], (i << 2) | (k >> 2));
+                const double piv = __shfl(m[k & 3], (k << 2) | (k >> 2));
+                double mk[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) mk[q] = __shfl(m[q], (k << 2) | (tid & 3));
+                const double r = 1.0 / piv;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = j0 + q;
+                    if (i == k && j == k) m[q] = r;
+                    else if (i == k) m[q] = mk[q] * r;
+                    else if (j == k) m[q] = -mik * r;
+                    else m[q] = m[q] - mik * mk[q] * r;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) M[i * kMaxDot + j0 + q] = m[q];
     }
+    __syncthreads();
+    const int i = tid >> 4, j = tid & 15;
+    const double m = M[tid];
     // exactly symmetric A (the energy tables and every kernel read this copy)
     const double a = (i < n && j < n) ? 0.5 * (m + M[j * kMaxDot + i]) : 0.0;
     __syncthreads();
@@ -355,10 +374,10 @@ __device__ inline void prep_inverse(const DiagRec *dr, double *M, double *cvec, 
     __syncthreads();
 }
 
-__device__ inline void prep_store(DiagRec *dr, const double *M, const double *cvec,
-                                  const double *red)
+// A, C_dd 1, 1^T C_dd 1 and sum|A|/2 into the record (one block)
+__device__ inline void prep_store_core(DiagRec *dr, const double *M, const double *cvec,
+                                       const double *red)
 {
-    const int n = dr->n;
     const int tid = threadIdx.x;
     dr->A[tid] = M[tid];
     if (tid < kMaxDot) dr->c[tid] = cvec[tid];
@@ -366,6 +385,66 @@ __device__ inline void prep_store(DiagRec *dr, const double *M, const double *cv
         dr->one_c = red[4];
         dr->sumabs = (float)red[5];
     }
+}
+
+// The energy tables from A in LDS, spread over the waves of a grid: entry e
+// (of 256) goes to global wave e mod (number of waves), whose 64 lanes take
+// the 8 x 8 products b_x b_y A_xy and sum them.
+__device__ inline void prep_tables_spread(DiagRec *dr, const double *M)
+{
+    const int n = dr->n;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gw = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int nw = gridDim.x * (blockDim.x / kWave);
+    const int x = lane >> 3, y = lane & 7;
+    const int nh = n - 8;
+    for (int e = gw; e < 256; e += nw) {
+        const bool both = (e >> x & 1) && (e >> y & 1);
+        double hl = 0.0, hh = 0.0;
+        if (n >= 9) {
+            hl = both ? M[x * kMaxDot + y] : 0.0;
+            hh = (both && x < nh && y < nh) ? M[(8 + x) * kMaxDot + 8 + y] : 0.0;
+        } else if (e < (1 << n)) {
+            hl = both ? M[x * kMaxDot + y] : 0.0;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            hl += __shfl_xor(hl, off, kWave);
+            hh += __shfl_xor(hh, off, kWave);
+        }
+        if (lane == 0) {
+            if (n >= 9) {
+                dr->hlo[e] = (float)(0.5 * hl);
+                dr->Hhi[e] = (e < (1 << nh)) ? (float)(0.5 * hh) : 1e30f;
+                dr->hlod[e] = 0.5 * hl;
+                dr->Hhid[e] = (e < (1 << nh)) ? 0.5 * hh : 1e300;
+                if (e < 16 * 8) {
+                    const int r = e >> 3, q = e & 7;
+                    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        if ((r >> b & 1) && b < nh) t1 += M[q * kMaxDot + 8 + b];
+                        if ((r >> b & 1) && b + 4 < nh) t2 += M[q * kMaxDot + 12 + b];
+                    }
+                    dr->T1[r][q] = (float)t1;
+                    dr->T2[r][q] = (float)t2;
+                    dr->T1d[r][q] = t1;
+                    dr->T2d[r][q] = t2;
+                }
+            } else {
+                dr->hs[e] = 0.5 * hl;
+            }
+        }
+    }
+}
+
+// everything the prologue stores, by one block
+__device__ inline void prep_store(DiagRec *dr, const double *M, const double *cvec,
+                                  const double *red)
+{
+    const int n = dr->n;
+    const int tid = threadIdx.x;
+    prep_store_core(dr, M, cvec, red);
     // tables of the matrix-core scorer: low part = dots 0..7, high = 8..n-1
     if (n >= 9) {
         const int nh = n - 8;

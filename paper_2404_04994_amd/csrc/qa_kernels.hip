@@ -153,15 +153,9 @@ __global__ __launch_bounds__(256) void k_setup(DiagRec *__restrict__ dr,
     __shared__ double sK[NM * NM];         // K (symmetric), identity beyond n
     __shared__ double sG[kMaxGate * NM];   // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
-    // the diagram prologue, in every block (a few microseconds of latency,
-    // no separate launch); block 0 also publishes A and the energy tables
-    // for the scoring kernels and clears the call's counters
+    // the diagram prologue, in every block (no separate launch); the blocks
+    // publish A and the energy tables for the scoring kernels at their end
     prep_inverse(dr, sA, sc, red);
-    if (blockIdx.x == 0) {
-        prep_store(dr, sA, sc, red);
-        if (counters)
-            for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0;
-    }
     const int n = dr->n, g = dr->g;
     const double one_c = red[4];
     for (int e = threadIdx.x; e < NM * NM; e += blockDim.x) {
@@ -288,6 +282,15 @@ __global__ __launch_bounds__(256) void k_setup(DiagRec *__restrict__ dr,
     // of this call are cleared by block 0 concurrently, so no atomics here
     __syncthreads();
     if (threadIdx.x < 4) bstats[blockIdx.x * 4 + threadIdx.x] = cnt[threadIdx.x];
+    // the diagram's record for the next kernels: block 0 stores A and the
+    // sums and clears the call's counters; the table entries are spread
+    // over the waves of the grid
+    if (blockIdx.x == 0) {
+        prep_store_core(dr, sA, sc, red);
+        if (counters)
+            for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0;
+    }
+    prep_tables_spread(dr, sA);
 }
 
 #define QA_DISPATCH_NM(n, CALL)                        \
