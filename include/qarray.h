@@ -117,9 +117,6 @@ typedef struct {
     int64_t near_tie_pixels;   /* approximate scoring flagged -> FP64 re-score */
     int64_t fp64_gap_below_1e9;/* pixels whose FP64 best/runner-up gap < 1e-9 */
     int64_t candidates;        /* candidate states scored (approximate pass) */
-    int64_t band_overflow;     /* near-tie pixels whose error band held more
-                                  states than the in-kernel re-score keeps;
-                                  they get a full FP64 pass instead */
 } qa_stats;
 
 /* Ground state at T = 0 (Sec. 3, Eq. argmin) of P pixels.
@@ -199,10 +196,11 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
                                   double *nbar_out_dev, qa_stats *stats, void *hip_stream);
 
 /* Stage timing (diagnostics).  While enabled, every ground-state call on a
- * stream records HIP events on that stream around its three stages:
+ * stream records HIP events on that stream around its stages:
  *   stage 0: prologue, continuous minimum and candidate setup,
- *   stage 1: candidate scoring (the matrix-core or FP64 scorer),
- *   stage 2: FP64 re-score of near-tie pixels (0 when not used).
+ *   stage 1: candidate scoring (the matrix-core or FP64 scorer, including
+ *            the FP64 re-score of near ties),
+ *   stage 2: work after the scorer (none in this build: 0).
  * qa_timing_reset() forgets earlier records of the stream;
  * qa_timing_sum() waits for the stream and writes the summed milliseconds
  * of each stage (ms_out[3]) over the calls recorded since the reset and the

@@ -4,10 +4,11 @@
 
 Each .hip file is compiled to an object, then linked into one shared
 library.  The matrix-core scorer gets two extra code-generation options:
-relaxed NaN handling with the IEEE mode bit off (its min reductions need no
-NaN quieting; no NaN can arise there) and the VGPR form of the MFMA
-instructions (results feed VALU minima directly, no accumulator-register
-copies).
+relaxed NaN handling (its min reductions need no NaN quieting; no NaN can
+arise there) and the VGPR form of the MFMA instructions (results feed VALU
+minima directly, no accumulator-register copies).  The IEEE mode bit is left
+on: turning it off for one file stops the device library's work-item
+queries from inlining into its kernels.
 """
 from __future__ import annotations
 
@@ -34,7 +35,7 @@ FLAGS = [
     "-Wno-unused-function",
 ]
 PER_FILE = {
-    "qa_mfma.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee", "-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "qa_mfma.hip": ["-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

@@ -50,8 +50,6 @@ struct Workspace {
     int64_t dr_cap = 0;
     PixRec *pr = nullptr;
     int64_t pr_cap = 0;
-    int32_t *flag_list = nullptr;
-    int64_t flag_cap = 0;
     int32_t *bstats = nullptr;          // per-block counts of the setup kernel
     int64_t bstats_cap = 0;
     int64_t bstats_used = 0;            // blocks of the last single-diagram setup
@@ -262,7 +260,6 @@ qa_status grow_single(Workspace *w, int64_t P)
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
     if (w->dr != dr0) w->dr_inputs.clear();
     if ((st = grow(w, w->pr, w->pr_cap, P))) return st;
-    if ((st = grow(w, w->flag_list, w->flag_cap, P))) return st;
     // four counts per setup block; N = 16 has the most blocks
     if ((st = grow(w, w->bstats, w->bstats_cap, 4 * setup_blocks(P, kMaxDot)))) return st;
     return QA_OK;
@@ -289,14 +286,11 @@ qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, cons
         QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else if (use_matrix_cores(pb)) {
-        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, n_out, w->flag_list,
-                                 w->counters, pb->n_dot, s));
+        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, n_out, w->counters, pb->n_dot,
+                                 s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
-        QA_HIP(launch_score_fp64(w->dr, w->pr, P, w->flag_list, w->counters + C_FLAG_LIST, n_out,
-                                 w->counters, pb->n_dot, s));
     } else {
-        QA_HIP(launch_score_fp64(w->dr, w->pr, P, nullptr, nullptr, n_out, w->counters,
-                                 pb->n_dot, s));
+        QA_HIP(launch_score_fp64(w->dr, w->pr, P, n_out, w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     }
     if (ev) QA_HIP(hipEventRecord((*ev)[3], s));
@@ -319,7 +313,6 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
                                 (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
                                 (int64_t)(uintptr_t)saved, (int64_t)(uintptr_t)w->dr,
                                 (int64_t)(uintptr_t)w->pr,
-                                (int64_t)(uintptr_t)w->flag_list,
                                 (int64_t)(uintptr_t)w->bstats};
     auto it = w->graphs.find(key);
     if (it == w->graphs.end()) {
@@ -373,7 +366,6 @@ qa_status read_stats(Workspace *w, qa_stats *stats)
     stats->near_tie_pixels = c[C_NEAR_TIE];
     stats->fp64_gap_below_1e9 = c[C_GAP_1E9];
     stats->candidates = c[C_CANDIDATES];
-    stats->band_overflow = c[C_BAND_OVERFLOW];
     return QA_OK;
 }
 
@@ -726,7 +718,6 @@ void qa_release(void *hip_stream)
     (void)hipStreamSynchronize(w->stream);
     (void)hipFree(w->dr);
     (void)hipFree(w->pr);
-    (void)hipFree(w->flag_list);
     (void)hipFree(w->bstats);
     (void)hipFree(w->counters);
     (void)hipFree(w->acc);

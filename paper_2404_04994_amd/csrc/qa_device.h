@@ -309,7 +309,7 @@ constexpr int kPrepThreads = 256;  // one thread per element of a 16 x 16 matrix
 // has checked definiteness by Cholesky).  Pivot k maps
 //   m_kk -> 1/p,  m_kj -> m_kj/p,  m_ik -> -m_ik/p,  m_ij -> m_ij - m_ik m_kj/p,
 // and after the n pivots M = C_dd^{-1}.  Dots beyond n stay identity rows.
-__device__ inline void prep_inverse(const DiagRec *dr, double *M, double *cvec, double *red)
+__device__ __forceinline__ void prep_inverse(const DiagRec *dr, double *M, double *cvec, double *red)
 {
     const int n = dr->n;
     const int tid = threadIdx.x;
@@ -375,7 +375,7 @@ __device__ inline void prep_inverse(const DiagRec *dr, double *M, double *cvec, 
 }
 
 // A, C_dd 1, 1^T C_dd 1 and sum|A|/2 into the record (one block)
-__device__ inline void prep_store_core(DiagRec *dr, const double *M, const double *cvec,
+__device__ __forceinline__ void prep_store_core(DiagRec *dr, const double *M, const double *cvec,
                                        const double *red)
 {
     const int tid = threadIdx.x;
@@ -390,7 +390,7 @@ __device__ inline void prep_store_core(DiagRec *dr, const double *M, const doubl
 // The energy tables from A in LDS, spread over the waves of a grid: entry e
 // (of 256) goes to global wave e mod (number of waves), whose 64 lanes take
 // the 8 x 8 products b_x b_y A_xy and sum them.
-__device__ inline void prep_tables_spread(DiagRec *dr, const double *M)
+__device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M)
 {
     const int n = dr->n;
     const int lane = threadIdx.x & (kWave - 1);
@@ -439,7 +439,7 @@ __device__ inline void prep_tables_spread(DiagRec *dr, const double *M)
 }
 
 // everything the prologue stores, by one block
-__device__ inline void prep_store(DiagRec *dr, const double *M, const double *cvec,
+__device__ __forceinline__ void prep_store(DiagRec *dr, const double *M, const double *cvec,
                                   const double *red)
 {
     const int n = dr->n;
@@ -489,7 +489,7 @@ __device__ inline void prep_store(DiagRec *dr, const double *M, const double *cv
     }
 }
 
-__device__ inline void prep_body(DiagRec *dr, double *M, double *cvec, double *red)
+__device__ __forceinline__ void prep_body(DiagRec *dr, double *M, double *cvec, double *red)
 {
     prep_inverse(dr, M, cvec, red);
     prep_store(dr, M, cvec, red);

@@ -25,8 +25,8 @@ constexpr int kWave = 64;
 // on one address from every block serialise at the memory side, so the
 // statistics are spread over kCounterSlots cache lines ([slot][C_NUM], a
 // block adds to slot blockIdx mod kCounterSlots) and summed by the host.
-// C_FLAG_LIST is a list cursor in slot 0 only; C_WORK is the cursor of one
-// shard of the batched kernel's work queue in every slot.
+// C_WORK is the cursor of one shard of the batched kernel's work queue in
+// every slot.
 constexpr int kCounterSlots = 64;
 enum Counter {
     C_PIXELS = 0,
@@ -37,8 +37,8 @@ enum Counter {
     C_GAP_1E9 = 5,
     C_CANDIDATES = 6,
     C_UNUSED7 = 7,
-    C_FLAG_LIST = 8,    // length of the full FP64 re-score list
-    C_BAND_OVERFLOW = 9,
+    C_UNUSED8 = 8,
+    C_UNUSED9 = 9,
     C_WORK = 10,        // work-queue shard cursor of the batched kernel
     C_NUM = 16
 };
@@ -128,14 +128,13 @@ int64_t setup_blocks(int64_t P, int n_dot);
 hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int64_t *counters,
                         int32_t *bstats, int n_dot, bool closed, hipStream_t s,
                         double *x_out = nullptr, int32_t *flags_out = nullptr);
-// T = 0 argmin in FP64 over the listed pixels (list == nullptr: all P)
-hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P,
-                             const int32_t *list, const int64_t *list_count,
-                             int32_t *n_out, int64_t *counters, int n_dot, hipStream_t s);
-// matrix-core scorer for the dense box at T = 0; flags near ties into flag_list
+// T = 0 argmin in FP64 over the candidate set of every pixel
+hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P, int32_t *n_out,
+                             int64_t *counters, int n_dot, hipStream_t s);
+// matrix-core scorer for the dense box at T = 0 (near ties re-scored in FP64
+// inside the kernel)
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
-                             int32_t *n_out, int32_t *flag_list, int64_t *counters,
-                             int n_dot, hipStream_t s);
+                             int32_t *n_out, int64_t *counters, int n_dot, hipStream_t s);
 hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
                            SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s);
 // adjoint partial sums into accA (kMaxDot^2), accG (kMaxDot x kMaxGate) and

@@ -328,16 +328,12 @@ hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int
 template <int LG, int NM>
 __global__ __launch_bounds__(256) void k_score_fp64(const DiagRec *__restrict__ dr,
                                                     const PixRec *__restrict__ pr, int64_t P,
-                                                    const int32_t *__restrict__ list,
-                                                    const int64_t *__restrict__ list_count,
                                                     int32_t *__restrict__ n_out,
                                                     int64_t *__restrict__ counters)
 {
     constexpr int G = 1 << LG;
     __shared__ double sA[kMaxDot * kMaxDot];
     __shared__ unsigned long long sc[2];
-    // list mode with an empty list (the usual case): nothing to do
-    if (list && *list_count == 0) return;
     for (int i = threadIdx.x; i < kMaxDot * kMaxDot; i += blockDim.x) sA[i] = dr->A[i];
     if (threadIdx.x < 2) sc[threadIdx.x] = 0;
     __syncthreads();
@@ -345,9 +341,7 @@ __global__ __launch_bounds__(256) void k_score_fp64(const DiagRec *__restrict__ 
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
-    const int64_t count = list ? *list_count : P;
-    for (int64_t it = gid; it < count; it += ngroups) {
-        const int64_t p = list ? list[it] : it;
+    for (int64_t p = gid; p < P; p += ngroups) {
         const PixRec *r = pr + p;
         double g0[NM];
 #pragma unroll
@@ -398,7 +392,7 @@ __global__ __launch_bounds__(256) void k_score_fp64(const DiagRec *__restrict__ 
     __syncthreads();
     if (threadIdx.x == 0) {
         block_add_counter(counters, C_GAP_1E9, (int64_t)sc[0]);
-        if (!list) block_add_counter(counters, C_CANDIDATES, (int64_t)sc[1]);
+        block_add_counter(counters, C_CANDIDATES, (int64_t)sc[1]);
     }
 }
 
@@ -435,16 +429,12 @@ static unsigned group_blocks(int64_t items, int lg, int64_t cap)
     return (unsigned)b;
 }
 
-hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P,
-                             const int32_t *list, const int64_t *list_count, int32_t *n_out,
+hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P, int32_t *n_out,
                              int64_t *counters, int n_dot, hipStream_t s)
 {
-    // list mode re-scores the few near-tie pixels whose band overflowed: a
-    // small grid strides over the list (its length is only known on device)
     QA_DISPATCH_GROUP(n_dot, hipLaunchKernelGGL((k_score_fp64<LG_, NM_>),
-                                                dim3(group_blocks(P, LG_, list ? 64 : 8192)),
-                                                dim3(256), 0, s, dr, pr, P, list, list_count, n_out,
-                                                counters));
+                                                dim3(group_blocks(P, LG_, 8192)), dim3(256), 0, s,
+                                                dr, pr, P, n_out, counters));
     return hipGetLastError();
 }
 

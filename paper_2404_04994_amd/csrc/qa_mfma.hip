@@ -59,7 +59,6 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi)
 }
 
 constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
-constexpr int kMaxBand = 256;  // near-tie states re-scored in FP64 inside the kernel
 
 #ifndef QA_SCORER_WAVES
 #define QA_SCORER_WAVES 3
@@ -69,7 +68,6 @@ template <int PREC>
 __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagRec *__restrict__ dr,
                                                     const PixRec *__restrict__ pr, int64_t P,
                                                     int32_t *__restrict__ n_out,
-                                                    int32_t *__restrict__ flag_list,
                                                     int64_t *__restrict__ counters)
 {
     __shared__ float sT1[16][8];
@@ -77,12 +75,10 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     __shared__ float sH[256];
     __shared__ double sT1d[16][8], sT2d[16][8];  // FP64 tables of the near-tie re-score
     __shared__ double sHd[256], sLd[256];
-    __shared__ int sband[4][kMaxBand];
-    __shared__ int sbandn[4];
     __shared__ double sG64[4][kMaxDot];
     __shared__ uint2 sCt[4][256];  // per wave: BF16 parts of C(c_hi) of its pixel
     __shared__ float sGm[4][16][64];  // per wave: lane minima of each row tile
-    __shared__ unsigned long long sflag, sover, sgap;
+    __shared__ unsigned long long sflag, sgap;
     for (int e = threadIdx.x; e < 128; e += blockDim.x) {
         sT1[e / 8][e % 8] = dr->T1[e / 8][e % 8];
         sT2[e / 8][e % 8] = dr->T2[e / 8][e % 8];
@@ -96,7 +92,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             sT2d[e / 8][e % 8] = dr->T2d[e / 8][e % 8];
         }
     }
-    if (threadIdx.x == 0) { sflag = 0; sover = 0; sgap = 0; }
+    if (threadIdx.x == 0) { sflag = 0; sgap = 0; }
     __syncthreads();
 
     const int n = dr->n;
@@ -143,7 +139,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     // of its pixel (vector loads, one pixel ahead).
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    int64_t nflag = 0, nover = 0, ngap = 0;
+    int64_t nflag = 0, ngap = 0;
     const int li = lane & 15;
     float *gmrec = &sGm[threadIdx.x >> 6][0][0];
     double gnext = 0.0;
@@ -373,66 +369,49 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             continue;
         }
         // ---- near tie: every candidate within 2 delta of the best holds the
-        // exact argmin; collect them and score them in FP64 ----
+        // exact argmin.  The wave sweeps the row tiles again (those whose lane
+        // minima all lie above the band are skipped) and each lane scores its
+        // own in-band states in FP64 from the split tables:
+        //   U(n0 + b) - U(n0) = b_lo^T (g_lo + A_LH b_hi) + h_lo(c_lo)
+        //                     + b_hi^T g_hi + 1/2 b_hi^T A_HH b_hi
+        // then the wave takes the smallest (ties to the lexicographically
+        // smallest state) ----
         ++nflag;
         const float thr = e1 + 2.0f * delta;
-        int *band = sband[threadIdx.x >> 6];
-        int *bandn = &sbandn[threadIdx.x >> 6];
-        if (lane == 0) *bandn = 0;
-        __builtin_amdgcn_wave_barrier();
-        for (int rt = 0; rt < nrt; ++rt) {
-            // row tiles whose lane minima all lie above the band hold none of it
-            if (!__ballot(gmrec[rt * 64 + lane] <= thr)) continue;
-            Pack8 a;
-            float af[3];
-            build_a(rt, a, af);
-#pragma unroll
-            for (int ct = 0; ct < 16; ++ct) {
-                const f32x4_t d = tile(a, af, ct);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (d[i] <= thr) {
-                        const int slot = atomicAdd(bandn, 1);
-                        if (slot < kMaxBand) {
-                            const uint32_t chi = (uint32_t)(rt * 16 + 4 * q + i);
-                            band[slot] = (int)((uint32_t)(ct * 16 + mrow) | (chi << 8));
-                        }
-                    }
-                }
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        const int cnt = *bandn;
-        if (cnt > kMaxBand) {
-            // too many states in the band: the full FP64 pass decides
-            if (lane == 0) {
-                const unsigned long long slot =
-                    atomicAdd((unsigned long long *)&counters[C_FLAG_LIST], 1ull);
-                flag_list[slot] = (int32_t)p;
-                ++nover;
-            }
-            continue;
-        }
         double *g64 = sG64[threadIdx.x >> 6];
         if (lane < kMaxDot) g64[lane] = gcur;
         __builtin_amdgcn_wave_barrier();
         double b1 = INFINITY, b2 = INFINITY;
         uint32_t c1 = 0;
-        for (int j = lane; j < cnt; j += 64) {
-            const uint32_t c = (uint32_t)band[j];
-            // the same split in FP64:
-            // U(n0 + b) - U(n0) = b_lo^T (g_lo + A_LH b_hi) + h_lo(c_lo)
-            //                   + b_hi^T g_hi + 1/2 b_hi^T A_HH b_hi
-            const uint32_t clo = c & 255u, chi = c >> 8;
-            const int row = chi & 15, rt = chi >> 4;
-            double e = sLd[clo] + sHd[chi];
+        for (int rt = 0; rt < nrt; ++rt) {
+            if (!__ballot(gmrec[rt * 64 + lane] <= thr)) continue;
+            Pack8 a;
+            float af[3];
+            build_a(rt, a, af);
+            uint64_t inband = 0;  // bit 4 ct + i: element i of tile ct
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (chi >> i & 1u) e += g64[8 + i];
-                if (clo >> i & 1u) e += (g64[i] + sT1d[row][i]) + sT2d[rt][i];
+            for (int ct = 0; ct < 16; ++ct) {
+                const f32x4_t d = tile(a, af, ct);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (d[i] <= thr) inband |= 1ull << (4 * ct + i);
             }
-            if (e < b1 || (e == b1 && __brev(c) < __brev(c1))) { b2 = b1; b1 = e; c1 = c; }
-            else b2 = fmin(b2, e);
+            while (inband) {
+                const int bit = __ffsll((long long)inband) - 1;
+                inband &= inband - 1;
+                const uint32_t clo = (uint32_t)((bit >> 2) * 16 + mrow);
+                const uint32_t chi = (uint32_t)(rt * 16 + 4 * q + (bit & 3));
+                const uint32_t c = clo | (chi << 8);
+                const int row = chi & 15, rth = chi >> 4;
+                double e = sLd[clo] + sHd[chi];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (chi >> i & 1u) e += g64[8 + i];
+                    if (clo >> i & 1u) e += (g64[i] + sT1d[row][i]) + sT2d[rth][i];
+                }
+                if (e < b1 || (e == b1 && __brev(c) < __brev(c1))) { b2 = b1; b1 = e; c1 = c; }
+                else b2 = fmin(b2, e);
+            }
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
@@ -450,13 +429,11 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     }
     if (lane == 0) {
         if (nflag) atomicAdd(&sflag, (unsigned long long)nflag);
-        if (nover) atomicAdd(&sover, (unsigned long long)nover);
         if (ngap) atomicAdd(&sgap, (unsigned long long)ngap);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         block_add_counter(counters, C_NEAR_TIE, (int64_t)sflag);
-        block_add_counter(counters, C_BAND_OVERFLOW, (int64_t)sover);
         block_add_counter(counters, C_GAP_1E9, (int64_t)sgap);
         // every pixel scores all 2^n candidates of its box on the matrix cores
         if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
@@ -485,8 +462,7 @@ static int resident_blocks(Kernel kernel, int slot)
 
 template <typename Kernel>
 static hipError_t launch_persistent(Kernel kernel, int slot, const DiagRec *dr, const PixRec *pr,
-                                    int64_t P, int32_t *n_out, int32_t *flag_list,
-                                    int64_t *counters, hipStream_t s)
+                                    int64_t P, int32_t *n_out, int64_t *counters, hipStream_t s)
 {
     // persistent waves: as many blocks as the chip keeps resident, at most
     // one wave per pixel
@@ -494,26 +470,23 @@ static hipError_t launch_persistent(Kernel kernel, int slot, const DiagRec *dr, 
     const int resident = resident_blocks(kernel, slot);
     if (resident > 0 && blocks > resident) blocks = resident;
     hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, s, dr, pr, P, n_out,
-                       flag_list, counters);
+                       counters);
     return hipGetLastError();
 }
 
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
-                             int32_t *n_out, int32_t *flag_list, int64_t *counters, int n_dot,
+                             int32_t *n_out, int64_t *counters, int n_dot,
                              hipStream_t s)
 {
     if (n_dot < 9 || n_dot > 16) return hipErrorInvalidValue;
     if (P <= 0) return hipSuccess;
     switch (prec) {
     case kPrecFP32:
-        return launch_persistent(k_score_mfma<kPrecFP32>, 0, dr, pr, P, n_out, flag_list,
-                                 counters, s);
+        return launch_persistent(k_score_mfma<kPrecFP32>, 0, dr, pr, P, n_out, counters, s);
     case kPrecX3:
-        return launch_persistent(k_score_mfma<kPrecX3>, 1, dr, pr, P, n_out, flag_list, counters,
-                                 s);
+        return launch_persistent(k_score_mfma<kPrecX3>, 1, dr, pr, P, n_out, counters, s);
     case kPrecX2:
-        return launch_persistent(k_score_mfma<kPrecX2>, 2, dr, pr, P, n_out, flag_list, counters,
-                                 s);
+        return launch_persistent(k_score_mfma<kPrecX2>, 2, dr, pr, P, n_out, counters, s);
     default:
         return hipErrorInvalidValue;
     }

@@ -42,7 +42,7 @@ class Problem(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(name, C.c_int64) for name in
                 ("pixels", "qp_pixels", "qp_failures", "doubled_pixels", "near_tie_pixels",
-                 "fp64_gap_below_1e9", "candidates", "band_overflow")]
+                 "fp64_gap_below_1e9", "candidates")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
