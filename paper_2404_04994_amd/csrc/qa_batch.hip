@@ -22,6 +22,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_batch(const BatchHdr *__r
                                                    const double *__restrict__ mats,
                                                    DiagRec *__restrict__ recs)
 {
+    __shared__ double sCdd[kMaxDot * kMaxDot];
     __shared__ double M[kMaxDot * kMaxDot];
     __shared__ double cvec[kMaxDot];
     __shared__ double red[8];
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_batch(const BatchHdr *__r
         dr->prec = 0;
     }
     __syncthreads();
-    prep_body(dr, M, cvec, red);
+    prep_body(dr, sCdd, M, cvec, red);
 }
 
 hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *recs, int n_diag,

@@ -309,9 +309,11 @@ constexpr int kPrepThreads = 256;  // one thread per element of a 16 x 16 matrix
 // has checked definiteness by Cholesky).  Pivot k maps
 //   m_kk -> 1/p,  m_kj -> m_kj/p,  m_ik -> -m_ik/p,  m_ij -> m_ij - m_ik m_kj/p,
 // and after the n pivots M = C_dd^{-1}.  Dots beyond n stay identity rows.
-__device__ __forceinline__ void prep_inverse(const DiagRec *dr, double *M, double *cvec, double *red)
+// sCdd: C_dd (kMaxDot x kMaxDot, row-major) already in LDS.  The caller
+// has passed a barrier after filling it.
+__device__ __forceinline__ void prep_inverse(const double *sCdd, int n, double *M, double *cvec,
+                                             double *red)
 {
-    const int n = dr->n;
     const int tid = threadIdx.x;
     if (tid < kWave) {
         // wave 0 eliminates in registers: lane l holds row l / 4, columns
@@ -322,7 +324,7 @@ __device__ __forceinline__ void prep_inverse(const DiagRec *dr, double *M, doubl
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = j0 + q;
-            m[q] = (i < n && j < n) ? dr->Cdd[i * kMaxDot + j] : (i == j ? 1.0 : 0.0);
+            m[q] = (i < n && j < n) ? sCdd[i * kMaxDot + j] : (i == j ? 1.0 : 0.0);
         }
 #pragma unroll
         for (int k = 0; k < kMaxDot; ++k) {
@@ -345,6 +347,17 @@ __device__ __forceinline__ void prep_inverse(const DiagRec *dr, double *M, doubl
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) M[i * kMaxDot + j0 + q] = m[q];
+    } else if (tid < kWave + kMaxDot) {
+        // meanwhile, 16 lanes of wave 1: C_dd 1 and 1^T C_dd 1
+        const int r = tid - kWave;
+        double c = 0.0;
+        if (r < n)
+            for (int q = 0; q < n; ++q) c += sCdd[r * kMaxDot + q];
+        cvec[r] = c;
+        double oc = c;
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) oc += __shfl_xor(oc, off, 16);
+        if (r == 0) red[4] = oc;
     }
     __syncthreads();
     const int i = tid >> 4, j = tid & 15;
@@ -358,17 +371,6 @@ __device__ __forceinline__ void prep_inverse(const DiagRec *dr, double *M, doubl
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) sa += __shfl_xor(sa, off, 64);
     if ((tid & 63) == 0) red[tid >> 6] = sa;
-    // C_dd 1 and 1^T C_dd 1 (row sums of the input, 16 lanes of wave 0)
-    if (tid < kMaxDot) {
-        double c = 0.0;
-        if (tid < n)
-            for (int q = 0; q < n; ++q) c += dr->Cdd[tid * kMaxDot + q];
-        cvec[tid] = c;
-        double oc = c;
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) oc += __shfl_xor(oc, off, 16);
-        if (tid == 0) red[4] = oc;
-    }
     __syncthreads();
     if (tid == 0) red[5] = 0.5 * (red[0] + red[1] + red[2] + red[3]);
     __syncthreads();
@@ -489,9 +491,13 @@ __device__ __forceinline__ void prep_store(DiagRec *dr, const double *M, const d
     }
 }
 
-__device__ __forceinline__ void prep_body(DiagRec *dr, double *M, double *cvec, double *red)
+// the whole prologue of one diagram by one block; sCdd is 256 doubles of LDS
+__device__ __forceinline__ void prep_body(DiagRec *dr, double *sCdd, double *M, double *cvec,
+                                          double *red)
 {
-    prep_inverse(dr, M, cvec, red);
+    sCdd[threadIdx.x] = dr->Cdd[threadIdx.x];
+    __syncthreads();
+    prep_inverse(sCdd, dr->n, M, cvec, red);
     prep_store(dr, M, cvec, red);
 }
 

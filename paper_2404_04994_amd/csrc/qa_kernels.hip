@@ -36,6 +36,7 @@ hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s)
 __global__ __launch_bounds__(kPrepThreads) void k_prep(DiagRec *dr_all, int64_t *counters,
                                                       double *zero, int64_t nzero)
 {
+    __shared__ double sCdd[kMaxDot * kMaxDot];
     __shared__ double M[kMaxDot * kMaxDot];
     __shared__ double cvec[kMaxDot];
     __shared__ double red[8];
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep(DiagRec *dr_all, int64_t 
         for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0;
     if (zero && blockIdx.x == 0)
         for (int64_t i = threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0.0;
-    prep_body(dr_all + blockIdx.x, M, cvec, red);
+    prep_body(dr_all + blockIdx.x, sCdd, M, cvec, red);
 }
 
 hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s, double *zero,
@@ -147,31 +148,35 @@ __global__ __launch_bounds__(256) void k_setup(DiagRec *__restrict__ dr,
                                                double *__restrict__ x_out,
                                                int32_t *__restrict__ flags_out)
 {
+    __shared__ double sCdd[kMaxDot * kMaxDot];  // C_dd (input)
     __shared__ double sA[kMaxDot * kMaxDot];  // A (symmetric), from the prologue
     __shared__ double sc[kMaxDot];            // C_dd 1
     __shared__ double red[8];
     __shared__ double sK[NM * NM];         // K (symmetric), identity beyond n
     __shared__ double sG[kMaxGate * NM];   // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
-    // the diagram prologue, in every block (no separate launch); the blocks
-    // publish A and the energy tables for the scoring kernels at their end
-    prep_inverse(dr, sA, sc, red);
+    // the inputs into LDS in one pass
     const int n = dr->n, g = dr->g;
-    const double one_c = red[4];
-    for (int e = threadIdx.x; e < NM * NM; e += blockDim.x) {
-        const int i = e / NM, j = e % NM;
-        double kv = (i == j) ? 1.0 : 0.0;
-        if (i < n && j < n) {
-            kv = dr->Cdd[i * kMaxDot + j];
-            if (CLOSED) kv -= sc[i] * sc[j] / one_c;
-        }
-        sK[e] = kv;
-    }
+    sCdd[threadIdx.x] = dr->Cdd[threadIdx.x];
     for (int e = threadIdx.x; e < kMaxGate * NM; e += blockDim.x) {
         const int j = e / NM, i = e % NM;
         sG[e] = dr->Cgd[i * kMaxGate + j];
     }
     if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    // the diagram prologue, in every block (no separate launch); the blocks
+    // publish A and the energy tables for the scoring kernels at their end
+    prep_inverse(sCdd, n, sA, sc, red);
+    const double one_c = red[4];
+    for (int e = threadIdx.x; e < NM * NM; e += blockDim.x) {
+        const int i = e / NM, j = e % NM;
+        double kv = (i == j) ? 1.0 : 0.0;
+        if (i < n && j < n) {
+            kv = sCdd[i * kMaxDot + j];
+            if (CLOSED) kv -= sc[i] * sc[j] / one_c;
+        }
+        sK[e] = kv;
+    }
     __syncthreads();
 
     const int dot = threadIdx.x & (NM - 1);
