@@ -85,8 +85,9 @@ typedef enum { QA_OPEN = 0, QA_CLOSED = 1 } qa_mode;
  * The integer result is the same for all four: the near-tie re-score
  * replaces the approximate argmin by the FP64 one whenever the approximate
  * runner-up lies within the certified error band.  The matrix-core forms are
- * used for the dense box (t = 1) of open arrays at T = 0 with n_dot >= 9;
- * elsewhere the FP64 form runs regardless of the request. */
+ * used for open arrays at T = 0 with n_dot >= 9, over the dense box (t = 1)
+ * or the thresholded sub-box of each pixel (t < 1, Sec. 3.2.2); elsewhere
+ * the FP64 form runs regardless of the request. */
 typedef enum {
     QA_PREC_FP64 = 0,
     QA_PREC_FP32 = 1,
@@ -171,7 +172,8 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
 size_t qa_saved_bytes(int64_t P, int32_t n_dot);
 
 /* A batch of independent diagrams (the dataset-generation use of Sec. 1)
- * in one graph-captured launch sequence.  Diagram d has its own problem
+ * in one launch sequence (prologue of every diagram, one persistent
+ * kernel over all pixels).  Diagram d has its own problem
  * probs[d] (N_d, G_d, mode, N_hat, kT, t; precision is ignored, every
  * energy is FP64) and its own P_d pixels.
  *   V_dev       : device FP64; diagram d's voltages are the P_d x G_d
@@ -207,11 +209,14 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
  * number of calls (at most 4096 are kept).  Off by default. */
 void qa_timing_enable(int on);
 
-/* Launch mode.  With graphs on (the default, or QA_GRAPHS=0 in the
- * environment to start with them off) each call replays a hipGraph captured
- * for its launch shape and buffers (captured on first use; the per-call
- * inputs are copied before the replay); off, every kernel is launched
- * directly.  Results are identical.  Stage timing always launches directly. */
+/* Launch mode.  Off (the default; QA_GRAPHS=1 in the environment starts
+ * with it on), every kernel is launched directly on the caller's stream.
+ * On, each call replays a hipGraph captured for its launch shape and
+ * buffers (captured on first use; the per-call inputs are copied before the
+ * replay).  Results are identical.  A call here is two or three kernels, and
+ * on ROCm 7 a graph launch costs more host and device time than launching
+ * them directly, so graphs are opt-in.  Stage timing always launches
+ * directly. */
 void qa_graphs_enable(int on);
 void qa_timing_reset(void *hip_stream);
 qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out);

@@ -66,6 +66,13 @@ struct Workspace {
     int64_t bmats_cap = 0;
     DiagRec *brecs = nullptr;
     int64_t brecs_cap = 0;
+    // pinned staging of the batch plan (headers, then matrices), two slots
+    // used in turn; a slot is rewritten only after its last copy has run
+    unsigned char *bstage[2] = {};
+    size_t bstage_cap[2] = {};
+    hipEvent_t bstage_ev[2] = {};
+    int bstage_next = 0;
+    std::vector<unsigned char> bplan_inputs;  // the plan last copied to bhdr / bmats
     hipStream_t cap_stream = nullptr;   // private stream used for graph capture
     hipGraphExec_t graph = nullptr;
     std::vector<int64_t> graph_key;
@@ -86,7 +93,7 @@ struct BatchTune {
     bool by_size;  // work order: diagrams with more candidates first
 };
 std::map<std::vector<int64_t>, BatchTune> g_tune;
-bool g_autotune_env_read = false, g_autotune = true, g_graphs = true;
+bool g_autotune_env_read = false, g_autotune = true, g_graphs = false;
 
 void read_env()
 {
@@ -267,8 +274,7 @@ qa_status grow_single(Workspace *w, int64_t P)
 
 bool use_matrix_cores(const qa_problem *pb)
 {
-    return pb->precision != QA_PREC_FP64 && pb->threshold >= 1.0 && pb->n_dot >= 9 &&
-           pb->mode == QA_OPEN;
+    return pb->precision != QA_PREC_FP64 && pb->n_dot >= 9 && pb->mode == QA_OPEN;
 }
 
 // The device work of one single-diagram call on stream s (inputs already in
@@ -286,8 +292,8 @@ qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, cons
         QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else if (use_matrix_cores(pb)) {
-        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, n_out, w->counters, pb->n_dot,
-                                 s));
+        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, pb->threshold < 1.0, n_out,
+                                 w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else {
         QA_HIP(launch_score_fp64(w->dr, w->pr, P, n_out, w->counters, pb->n_dot, s));
@@ -308,7 +314,7 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
     w->bstats_used = setup_blocks(P, pb->n_dot);
     std::array<hipEvent_t, 4> *ev = timing_slot(w);
     if (ev || !g_graphs) return enqueue_single(w, w->stream, pb, V, P, n_out, nbar, saved, ev);
-    const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + pb->precision : 1);
+    const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + 2 * pb->precision + (pb->threshold < 1.0) : 1);
     std::vector<int64_t> key = {pb->n_dot, pb->mode, path, P, (int64_t)(uintptr_t)V,
                                 (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
                                 (int64_t)(uintptr_t)saved, (int64_t)(uintptr_t)w->dr,
@@ -524,13 +530,44 @@ void plan_batch(const qa_problem *probs, int32_t n_diag, const int64_t *v_offset
 qa_status upload_plan(Workspace *w, const BatchPlan &plan, int32_t n_diag)
 {
     qa_status st;
+    const BatchHdr *h0 = w->bhdr;
+    const double *m0 = w->bmats;
     if ((st = grow(w, w->bhdr, w->bhdr_cap, n_diag))) return st;
     if ((st = grow(w, w->bmats, w->bmats_cap, (int64_t)plan.mats.size()))) return st;
     if ((st = grow(w, w->brecs, w->brecs_cap, n_diag))) return st;
-    QA_HIP(hipMemcpyAsync(w->bhdr, plan.hdr.data(), sizeof(BatchHdr) * n_diag,
-                          hipMemcpyHostToDevice, w->stream));
-    QA_HIP(hipMemcpyAsync(w->bmats, plan.mats.data(), sizeof(double) * plan.mats.size(),
-                          hipMemcpyHostToDevice, w->stream));
+    if (w->bhdr != h0 || w->bmats != m0) w->bplan_inputs.clear();
+    const size_t nh = sizeof(BatchHdr) * n_diag, nm = sizeof(double) * plan.mats.size();
+    const unsigned char *hb = reinterpret_cast<const unsigned char *>(plan.hdr.data());
+    const unsigned char *mb = reinterpret_cast<const unsigned char *>(plan.mats.data());
+    // the same plan as the last upload on this stream: the device copies hold it
+    if (w->bplan_inputs.size() == nh + nm && std::memcmp(w->bplan_inputs.data(), hb, nh) == 0 &&
+        std::memcmp(w->bplan_inputs.data() + nh, mb, nm) == 0)
+        return QA_OK;
+    // through pinned memory, so the copy is asynchronous (a pageable source
+    // makes the runtime wait for the stream)
+    const int slot = w->bstage_next;
+    w->bstage_next ^= 1;
+    if (!w->bstage_ev[slot])
+        QA_HIP(hipEventCreateWithFlags(&w->bstage_ev[slot], hipEventDisableTiming));
+    QA_HIP(hipEventSynchronize(w->bstage_ev[slot]));
+    if (w->bstage_cap[slot] < nh + nm) {
+        if (w->bstage[slot]) QA_HIP(hipHostFree(w->bstage[slot]));
+        w->bstage[slot] = nullptr;
+        w->bstage_cap[slot] = 0;
+        const size_t cap = (nh + nm) * 5 / 4 + 4096;
+        if (hipHostMalloc((void **)&w->bstage[slot], cap) != hipSuccess) {
+            w->bstage[slot] = nullptr;
+            return fail(QA_E_WORKSPACE, "hipHostMalloc of %zu bytes of batch staging failed", cap);
+        }
+        w->bstage_cap[slot] = cap;
+    }
+    unsigned char *stg = w->bstage[slot];
+    std::memcpy(stg, hb, nh);
+    std::memcpy(stg + nh, mb, nm);
+    w->bplan_inputs.assign(stg, stg + nh + nm);
+    QA_HIP(hipMemcpyAsync(w->bhdr, stg, nh, hipMemcpyHostToDevice, w->stream));
+    if (nm) QA_HIP(hipMemcpyAsync(w->bmats, stg + nh, nm, hipMemcpyHostToDevice, w->stream));
+    QA_HIP(hipEventRecord(w->bstage_ev[slot], w->stream));
     return QA_OK;
 }
 
@@ -726,6 +763,10 @@ void qa_release(void *hip_stream)
     (void)hipFree(w->bhdr);
     (void)hipFree(w->bmats);
     (void)hipFree(w->brecs);
+    for (int i = 0; i < 2; ++i) {
+        if (w->bstage[i]) (void)hipHostFree(w->bstage[i]);
+        if (w->bstage_ev[i]) (void)hipEventDestroy(w->bstage_ev[i]);
+    }
     if (w->graph) (void)hipGraphExecDestroy(w->graph);
     for (auto &kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
     if (w->stage) (void)hipHostFree(w->stage);

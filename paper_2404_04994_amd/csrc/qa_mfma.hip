@@ -1,5 +1,6 @@
-// qa_mfma.hip -- matrix-core scorer for the dense floor/ceil box (Sec. 3.2.1)
-// at T = 0 (Eq. argmin), 9 <= N <= 16 dots, open arrays.
+// qa_mfma.hip -- matrix-core scorer for the floor/ceil box (Sec. 3.2.1) and
+// its thresholded sub-boxes (Sec. 3.2.2) at T = 0 (Eq. argmin), 9 <= N <= 16
+// dots, open arrays.
 //
 // Every candidate of pixel p is n0 + b, b in {0,1}^N, and (Eq. free_energy)
 //     U(n0 + b) - U(n0) = b^T g + 1/2 b^T A b,       g = A (n0 - x_u).
@@ -26,9 +27,9 @@
 // runner-up inside it.  When the runner-up lies within twice the certified
 // error bound of the best, the exact argmin is one of the states whose
 // approximate energy lies within that band of the best: the wave sweeps the
-// box once more, collects those states (at most 256) and scores them in FP64
-// (ties to the lexicographically smallest state); a larger band sends the
-// pixel to the full FP64 scorer.  Otherwise n* = n0 + b is written directly.
+// row tiles that hold such states once more and every lane scores its own
+// in-band states in FP64 (ties to the lexicographically smallest state).
+// Otherwise n* = n0 + b is written directly.
 #include "qa_internal.h"
 
 namespace qa {
@@ -64,7 +65,14 @@ constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
 #define QA_SCORER_WAVES 3
 #endif
 
-template <int PREC>
+// PRUNED: the thresholded candidate set (Sec. 3.2.2), n0 + b with b a subset
+// of the pixel's free dots.  A fixed dot i gets the penalty 2^100 added to
+// g_i, so every state that raises it scores above 2^99 and never wins, and
+// the tables are unchanged; row tiles that raise a fixed dot of 12..15 and
+// column tiles that raise a fixed dot of 4..7 are skipped.  A 0/1 operand
+// times the penalty is an exact 0 or the penalty, so the valid states score
+// exactly as in the dense form and the same error bound holds for them.
+template <int PREC, bool PRUNED>
 __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagRec *__restrict__ dr,
                                                     const PixRec *__restrict__ pr, int64_t P,
                                                     int32_t *__restrict__ n_out,
@@ -78,7 +86,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     __shared__ double sG64[4][kMaxDot];
     __shared__ uint2 sCt[4][256];  // per wave: BF16 parts of C(c_hi) of its pixel
     __shared__ float sGm[4][16][64];  // per wave: lane minima of each row tile
-    __shared__ unsigned long long sflag, sgap;
+    __shared__ unsigned long long sflag, sgap, scand;
     for (int e = threadIdx.x; e < 128; e += blockDim.x) {
         sT1[e / 8][e % 8] = dr->T1[e / 8][e % 8];
         sT2[e / 8][e % 8] = dr->T2[e / 8][e % 8];
@@ -92,7 +100,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             sT2d[e / 8][e % 8] = dr->T2d[e / 8][e % 8];
         }
     }
-    if (threadIdx.x == 0) { sflag = 0; sgap = 0; }
+    if (threadIdx.x == 0) { sflag = 0; sgap = 0; scand = 0; }
     __syncthreads();
 
     const int n = dr->n;
@@ -139,32 +147,44 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     // of its pixel (vector loads, one pixel ahead).
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    int64_t nflag = 0, ngap = 0;
+    int64_t nflag = 0, ngap = 0, ncand = 0;
     const int li = lane & 15;
     float *gmrec = &sGm[threadIdx.x >> 6][0][0];
     double gnext = 0.0;
     int nnext = 0;
+    uint32_t fnext = 0;
     if (wave < P) {
         gnext = pr[wave].g0[li];
         nnext = pr[wave].n0[li];
+        if (PRUNED) fnext = pr[wave].free;
     }
     for (int64_t pw = wave; pw < P; pw += nwaves) {
         const int64_t p = pw;
         const double gcur = gnext;
         const int ncur = nnext;
+        // free dots of the pixel (a wave-uniform value)
+        const uint32_t F = PRUNED ? __builtin_amdgcn_readfirstlane(fnext) : 0xFFFFu;
         if (pw + nwaves < P) {
             gnext = pr[pw + nwaves].g0[li];
             nnext = pr[pw + nwaves].n0[li];
+            if (PRUNED) fnext = pr[pw + nwaves].free;
         }
         // g0 beyond n is zero in the record; every lane gets all sixteen
+        // (the error bound takes the unpenalised values)
         const float gl = (float)gcur;
+        const float glp = (PRUNED && !(F >> li & 1u)) ? 0x1p100f : gl;
         float g[16];
         float gabs = 0.0f;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i));
-            gabs += fabsf(g[i]);
+            g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(glp), i));
+            gabs += fabsf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i)));
         }
+        if (PRUNED) ncand += 1ll << __popc(F & ((1u << n) - 1u));
+        // row tiles (high dots 12..15) and column tiles (low dots 4..7) that
+        // raise no fixed dot
+        auto rt_ok = [&](int rt) { return !PRUNED || !(((uint32_t)rt << 12) & ~F); };
+        auto ct_ok = [&](int ct) { return !PRUNED || !(((uint32_t)ct << 4) & ~F); };
         // per-lane row constants: G1 = g_lo + A_LH b_hi(row bits), P1 = b_hi(row)^T g_hi
         float G1[8];
 #pragma unroll
@@ -275,23 +295,34 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
         float best1 = INFINITY, best2 = INFINITY;
         int rt1 = 0;
         for (int rt = 0; rt < nrt; ++rt) {
+            if (!rt_ok(rt)) continue;
             Pack8 a;
             float af[3];
             build_a(rt, a, af);
             // software-pipelined: the minima of tile ct - 1 are taken while
             // tile ct is on the matrix core (two independent minimum chains)
             float gm = INFINITY, gm2 = INFINITY;
-            f32x4_t dp = tile(a, af, 0);
+            if (PRUNED) {
 #pragma unroll
-            for (int ct = 1; ct < 16; ++ct) {
-                const f32x4_t d = tile(a, af, ct);
-                float &m = (ct & 1) ? gm : gm2;
-                m = fminf(fminf(m, dp[0]), dp[1]);
-                m = fminf(fminf(m, dp[2]), dp[3]);
-                dp = d;
+                for (int ct = 0; ct < 16; ++ct) {
+                    if (!ct_ok(ct)) continue;
+                    const f32x4_t d = tile(a, af, ct);
+                    gm = fminf(fminf(gm, d[0]), d[1]);
+                    gm2 = fminf(fminf(gm2, d[2]), d[3]);
+                }
+            } else {
+                f32x4_t dp = tile(a, af, 0);
+#pragma unroll
+                for (int ct = 1; ct < 16; ++ct) {
+                    const f32x4_t d = tile(a, af, ct);
+                    float &m = (ct & 1) ? gm : gm2;
+                    m = fminf(fminf(m, dp[0]), dp[1]);
+                    m = fminf(fminf(m, dp[2]), dp[3]);
+                    dp = d;
+                }
+                gm2 = fminf(fminf(gm2, dp[0]), dp[1]);
+                gm2 = fminf(fminf(gm2, dp[2]), dp[3]);
             }
-            gm2 = fminf(fminf(gm2, dp[0]), dp[1]);
-            gm2 = fminf(fminf(gm2, dp[2]), dp[3]);
             gm = fminf(gm, gm2);
             gmrec[rt * 64 + lane] = gm;
             if (gm < best1) { best2 = best1; best1 = gm; rt1 = rt; }
@@ -320,6 +351,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             int ct1 = 0;
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct) {
+                if (!ct_ok(ct)) continue;
                 const f32x4_t d = tile(a, af, ct);
                 const float tm = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
                 const bool lt = tm < t1;
@@ -384,13 +416,14 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
         double b1 = INFINITY, b2 = INFINITY;
         uint32_t c1 = 0;
         for (int rt = 0; rt < nrt; ++rt) {
-            if (!__ballot(gmrec[rt * 64 + lane] <= thr)) continue;
+            if (!rt_ok(rt) || !__ballot(gmrec[rt * 64 + lane] <= thr)) continue;
             Pack8 a;
             float af[3];
             build_a(rt, a, af);
             uint64_t inband = 0;  // bit 4 ct + i: element i of tile ct
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct) {
+                if (!ct_ok(ct)) continue;
                 const f32x4_t d = tile(a, af, ct);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -430,13 +463,15 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     if (lane == 0) {
         if (nflag) atomicAdd(&sflag, (unsigned long long)nflag);
         if (ngap) atomicAdd(&sgap, (unsigned long long)ngap);
+        if (ncand) atomicAdd(&scand, (unsigned long long)ncand);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         block_add_counter(counters, C_NEAR_TIE, (int64_t)sflag);
         block_add_counter(counters, C_GAP_1E9, (int64_t)sgap);
-        // every pixel scores all 2^n candidates of its box on the matrix cores
-        if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
+        // dense: every pixel scores all 2^n candidates of its box
+        if (PRUNED) block_add_counter(counters, C_CANDIDATES, (int64_t)scand);
+        else if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
     }
 }
 
@@ -475,18 +510,24 @@ static hipError_t launch_persistent(Kernel kernel, int slot, const DiagRec *dr, 
 }
 
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
-                             int32_t *n_out, int64_t *counters, int n_dot,
+                             bool pruned, int32_t *n_out, int64_t *counters, int n_dot,
                              hipStream_t s)
 {
     if (n_dot < 9 || n_dot > 16) return hipErrorInvalidValue;
     if (P <= 0) return hipSuccess;
-    switch (prec) {
-    case kPrecFP32:
-        return launch_persistent(k_score_mfma<kPrecFP32>, 0, dr, pr, P, n_out, counters, s);
-    case kPrecX3:
-        return launch_persistent(k_score_mfma<kPrecX3>, 1, dr, pr, P, n_out, counters, s);
-    case kPrecX2:
-        return launch_persistent(k_score_mfma<kPrecX2>, 2, dr, pr, P, n_out, counters, s);
+    switch (prec * 2 + (pruned ? 1 : 0)) {
+    case kPrecFP32 * 2:
+        return launch_persistent(k_score_mfma<kPrecFP32, false>, 0, dr, pr, P, n_out, counters, s);
+    case kPrecX3 * 2:
+        return launch_persistent(k_score_mfma<kPrecX3, false>, 1, dr, pr, P, n_out, counters, s);
+    case kPrecX2 * 2:
+        return launch_persistent(k_score_mfma<kPrecX2, false>, 2, dr, pr, P, n_out, counters, s);
+    case kPrecFP32 * 2 + 1:
+        return launch_persistent(k_score_mfma<kPrecFP32, true>, 3, dr, pr, P, n_out, counters, s);
+    case kPrecX3 * 2 + 1:
+        return launch_persistent(k_score_mfma<kPrecX3, true>, 4, dr, pr, P, n_out, counters, s);
+    case kPrecX2 * 2 + 1:
+        return launch_persistent(k_score_mfma<kPrecX2, true>, 5, dr, pr, P, n_out, counters, s);
     default:
         return hipErrorInvalidValue;
     }

@@ -70,16 +70,26 @@ def test_ragged_with_large_and_thresholded(qa, oracle):
 
 
 def test_batch_replays_and_no_nbar(qa, oracle):
-    """The captured graph replays; a second batch with other sizes re-captures;
-    nbar may be omitted."""
+    """Repeated runs of one batch, launched directly and as graph replays, give
+    the first result; the same layout with other matrices (identical headers,
+    so only the matrix part of the uploaded plan differs) is uploaded again;
+    a batch with other sizes re-plans; nbar may be omitted."""
     ds = W.ragged_batch(10, npix=16, start=200)
     b = qa.Batch(ds)
     b.run()
     first = b.n.clone()
-    for _ in range(3):
-        b.run()
-        torch.cuda.synchronize()
-        assert torch.equal(first, b.n)
+    try:
+        for graphs in (False, True):
+            qa.graphs_enable(graphs)
+            for _ in range(3):
+                b.run()
+                torch.cuda.synchronize()
+                assert torch.equal(first, b.n), graphs
+    finally:
+        qa.graphs_enable(False)
+    for d in ds:
+        d.cgd = d.cgd * 1.07
+    check_batch(qa, oracle, ds)
     check_batch(qa, oracle, W.ragged_batch(7, npix=20, start=300), with_nbar=False)
 
 

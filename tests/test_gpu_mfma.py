@@ -31,20 +31,23 @@ def say(*a):
     sys.stdout.flush()
 
 
-def compare(qa, oracle, d, prec, idx=None):
+def compare(qa, oracle, d, prec, idx=None, t=1.0):
     V = torch.as_tensor(d.V).cuda()
-    n, st = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True)
+    n, st = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, t=t)
     n = n.cpu().numpy()
     if idx is None:
         idx = np.arange(d.P)
-    ref = oracle.method_gs(d.cdd, d.cgd, d.V[idx])
+    ref = oracle.method_gs(d.cdd, d.cgd, d.V[idx], t=t)
     excl = (ref["e2"] - ref["e1"] < 1e-9) | ((ref["info"] & oracle.INFO_AMBIGUOUS) > 0)
     bad = (n[idx] != ref["n"]).any(1) & ~excl
-    say("N=%d P=%d checked=%d prec=%s mismatches=%d excluded=%d near_tie=%d qp=%d"
-        % (d.n_dot, d.P, len(idx), prec, bad.sum(), excl.sum(), st["near_tie_pixels"],
-           st["qp_pixels"]))
+    say("N=%d P=%d t=%.3f checked=%d prec=%s mismatches=%d excluded=%d near_tie=%d qp=%d "
+        "candidates=%d" % (d.n_dot, d.P, t, len(idx), prec, bad.sum(), excl.sum(),
+                           st["near_tie_pixels"], st["qp_pixels"], st["candidates"]))
     assert bad.sum() == 0, np.where(bad)[0][:10]
-    assert st["candidates"] == d.P << d.n_dot
+    if t >= 1.0:
+        assert st["candidates"] == d.P << d.n_dot
+    elif len(idx) == d.P:
+        assert st["candidates"] == ref["ncand"].sum()
     return n, st
 
 
@@ -94,6 +97,33 @@ def test_partial_high_index(qa, oracle, n_dot):
         compare(qa, oracle, d, prec)
 
 
+@pytest.mark.parametrize("t", [2 / 3, 0.5, 1 / 3, 0.1, 0.0])
+@pytest.mark.parametrize("prec", PRECS)
+def test_grid16_thresholded(qa, oracle, prec, t):
+    """Thresholded candidate sets (Sec. 3.2.2) on the matrix cores: each
+    pixel scores only the sub-box of its free dots; every pixel of a 40 x 40
+    sweep against the oracle's replay at the same t, and the number of
+    candidates equals the sum of the sub-box sizes."""
+    d = W.grid4x4(203, npix=40)
+    compare(qa, oracle, d, prec, t=t)
+
+
+@pytest.mark.parametrize("n_dot", [9, 11, 13, 16])
+def test_thresholded_partial_high_index(qa, oracle, n_dot):
+    """Sub-boxes on 9..16 dots: the fixed-dot penalty and the tile skips
+    combine with the absent high dots of N < 16."""
+    rng = np.random.default_rng(50 + n_dot)
+    cdd = np.diag(rng.uniform(1.0, 1.4, n_dot))
+    for i in range(n_dot - 1):
+        cdd[i, i + 1] = cdd[i + 1, i] = -rng.uniform(0.1, 0.3)
+    cgd = np.diag(rng.uniform(0.5, 1.0, n_dot))
+    V = rng.uniform(-1, 6, (700, n_dot))
+    d = W.Diagram(cdd, cgd, V)
+    for t in (0.8, 0.5, 0.25):
+        compare(qa, oracle, d, "bf16x3", t=t)
+    compare(qa, oracle, d, "fp32", t=0.5)
+
+
 def test_ragged_pixel_count(qa, oracle):
     d = W.grid4x4(202, npix=40)
     for P in (1, 5, 63, 1001):
@@ -112,16 +142,19 @@ def test_graph_replays_match_eager(qa, oracle):
     ref = qa.ground_state(d.cdd, d.cgd, V, precision="bf16x3").cpu()
     ref_soft, _ = qa.soft_charge(c.cdd, c.cgd, Vc, 0.02)
     ref_soft = ref_soft.cpu()
-    qa.graphs_enable(True)
-    out = torch.empty_like(ref).cuda()
-    for i in range(5):
-        qa.ground_state(d.cdd, d.cgd, V, precision="bf16x3", out=out)
-        torch.cuda.synchronize()
-        assert torch.equal(out.cpu(), ref), i
-        qa.graphs_enable(False)
-        qa.ground_state(c.cdd, c.cgd, Vc)           # eager work between replays
-        torch.cuda.synchronize()
+    try:
         qa.graphs_enable(True)
-        nb, _ = qa.soft_charge(c.cdd, c.cgd, Vc, 0.02)
-        torch.cuda.synchronize()
-        assert torch.equal(nb.cpu(), ref_soft), i
+        out = torch.empty_like(ref).cuda()
+        for i in range(5):
+            qa.ground_state(d.cdd, d.cgd, V, precision="bf16x3", out=out)
+            torch.cuda.synchronize()
+            assert torch.equal(out.cpu(), ref), i
+            qa.graphs_enable(False)
+            qa.ground_state(c.cdd, c.cgd, Vc)           # eager work between replays
+            torch.cuda.synchronize()
+            qa.graphs_enable(True)
+            nb, _ = qa.soft_charge(c.cdd, c.cgd, Vc, 0.02)
+            torch.cuda.synchronize()
+            assert torch.equal(nb.cpu(), ref_soft), i
+    finally:
+        qa.graphs_enable(False)
