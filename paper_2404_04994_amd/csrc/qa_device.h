@@ -376,12 +376,71 @@ __device__ __forceinline__ void prep_inverse(const double *sCdd, int n, double *
     __syncthreads();
 }
 
+// Wave 0 alone (no block barrier): the symmetric A = C_dd^{-1} into M and
+// sum|A|/2 into red[5], by the same elimination as prep_inverse.  The other
+// waves of the block may be doing anything meanwhile; the caller's next
+// block barrier publishes M.
+__device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, double *M,
+                                                  double *red)
+{
+    const int tid = threadIdx.x;
+    const int i = tid >> 2, j0 = 4 * (tid & 3);
+    double m[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q;
+        m[q] = (i < n && j < n) ? sCdd[i * kMaxDot + j] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxDot; ++k) {
+        if (k < n) {
+            const double mik = __shfl(m[k & 3], (i << 2) | (k >> 2));
+            const double piv = __shfl(m[k & 3], (k << 2) | (k >> 2));
+            double mk[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) mk[q] = __shfl(m[q], (k << 2) | (tid & 3));
+            const double r = 1.0 / piv;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + q;
+                if (i == k && j == k) m[q] = r;
+                else if (i == k) m[q] = mk[q] * r;
+                else if (j == k) m[q] = -mik * r;
+                else m[q] = m[q] - mik * mk[q] * r;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) M[i * kMaxDot + j0 + q] = m[q];
+    // exactly symmetric A: each lane reads the transposed entries (LDS
+    // requests of one wave are served in order, so every lane's read of the
+    // first pass precedes every write of the second)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double a[4], sa = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q;
+        a[q] = (i < n && j < n) ? 0.5 * (m[q] + M[j * kMaxDot + i]) : 0.0;
+        sa += fabs(a[q]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int q = 0; q < 4; ++q) M[i * kMaxDot + j0 + q] = a[q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sa += __shfl_xor(sa, off, 64);
+    if (tid == 0) red[5] = 0.5 * sa;
+}
+
 // A, C_dd 1, 1^T C_dd 1 and sum|A|/2 into the record (one block)
 __device__ __forceinline__ void prep_store_core(DiagRec *dr, const double *M, const double *cvec,
                                        const double *red)
 {
     const int tid = threadIdx.x;
-    dr->A[tid] = M[tid];
+    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) dr->A[e] = M[e];
     if (tid < kMaxDot) dr->c[tid] = cvec[tid];
     if (tid == 0) {
         dr->one_c = red[4];

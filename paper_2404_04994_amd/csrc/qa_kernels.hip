@@ -139,149 +139,184 @@ __device__ __forceinline__ void gj_pivot(double (&r)[NM], double &v, int k, int 
     }
 }
 
+// The block is eight waves: wave 0 inverts C_dd (the diagram prologue, in
+// every block, so that no prologue launch precedes this one) while waves 1-7
+// take 7 * 64 / NM pixels through x_u, the QP and the candidate set, which
+// need C_dd but not its inverse; a barrier then hands A to the pixel waves
+// for the base-state gradient.  (Eight waves: two blocks fill a CU at four
+// waves per SIMD; five-wave blocks left a fifth of the grid waiting for a
+// second round.)
+constexpr int kSetupPixThreads = 7 * kWave;
+constexpr int kSetupThreads = kWave + kSetupPixThreads;
+
 template <int NM, bool CLOSED>
-__global__ __launch_bounds__(256) void k_setup(DiagRec *__restrict__ dr,
-                                               const double *__restrict__ V, int64_t P,
-                                               PixRec *__restrict__ pr,
-                                               int64_t *__restrict__ counters,
-                                               int32_t *__restrict__ bstats,
-                                               double *__restrict__ x_out,
-                                               int32_t *__restrict__ flags_out)
+__global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec *__restrict__ dr,
+                                                         const double *__restrict__ V, int64_t P,
+                                                         PixRec *__restrict__ pr,
+                                                         int64_t *__restrict__ counters,
+                                                         int32_t *__restrict__ bstats,
+                                                         double *__restrict__ x_out,
+                                                         int32_t *__restrict__ flags_out)
 {
     __shared__ double sCdd[kMaxDot * kMaxDot];  // C_dd (input)
-    __shared__ double sA[kMaxDot * kMaxDot];  // A (symmetric), from the prologue
-    __shared__ double sc[kMaxDot];            // C_dd 1
-    __shared__ double red[8];
-    __shared__ double sK[NM * NM];         // K (symmetric), identity beyond n
-    __shared__ double sG[kMaxGate * NM];   // C_gd transposed: sG[j * NM + i]
+    __shared__ double sA[kMaxDot * kMaxDot];    // A (symmetric), from wave 0
+    __shared__ double sc[kMaxDot];              // C_dd 1
+    __shared__ double red[8];                   // [4] 1^T C_dd 1, [5] sum|A| / 2
+    __shared__ double sG[kMaxGate * NM];        // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
-    // the inputs into LDS in one pass
+    // the inputs into LDS in one pass; meanwhile 16 lanes of wave 0 form
+    // C_dd 1 and 1^T C_dd 1 from the record
     const int n = dr->n, g = dr->g;
-    sCdd[threadIdx.x] = dr->Cdd[threadIdx.x];
+    for (int e = threadIdx.x; e < kMaxDot * kMaxDot; e += blockDim.x) sCdd[e] = dr->Cdd[e];
     for (int e = threadIdx.x; e < kMaxGate * NM; e += blockDim.x) {
         const int j = e / NM, i = e % NM;
         sG[e] = dr->Cgd[i * kMaxGate + j];
     }
     if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    // the diagram prologue, in every block (no separate launch); the blocks
-    // publish A and the energy tables for the scoring kernels at their end
-    prep_inverse(sCdd, n, sA, sc, red);
-    const double one_c = red[4];
-    for (int e = threadIdx.x; e < NM * NM; e += blockDim.x) {
-        const int i = e / NM, j = e % NM;
-        double kv = (i == j) ? 1.0 : 0.0;
-        if (i < n && j < n) {
-            kv = sCdd[i * kMaxDot + j];
-            if (CLOSED) kv -= sc[i] * sc[j] / one_c;
-        }
-        sK[e] = kv;
+    if (threadIdx.x < kMaxDot) {
+        // the row's loads all issued before the first add
+        const int r = threadIdx.x;
+        double row[kMaxDot];
+#pragma unroll
+        for (int q = 0; q < kMaxDot; ++q) row[q] = (r < n && q < n) ? dr->Cdd[r * kMaxDot + q] : 0.0;
+        double c = 0.0;
+#pragma unroll
+        for (int q = 0; q < kMaxDot; ++q) c += row[q];
+        sc[r] = c;
+        double oc = c;
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) oc += __shfl_xor(oc, off, 16);
+        if (r == 0) red[4] = oc;
     }
     __syncthreads();
+    const double one_c = red[4];
 
-    const int dot = threadIdx.x & (NM - 1);
+    const bool pixel_wave = threadIdx.x >= kWave;
+    const int tp = threadIdx.x - kWave;  // thread index among the pixel waves
+    const int dot = tp & (NM - 1);
     const int base = (threadIdx.x & (kWave - 1)) & ~(NM - 1);
-    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / NM) + threadIdx.x / NM;
+    const int64_t p = (int64_t)blockIdx.x * (kSetupPixThreads / NM) + tp / NM;
     const int64_t pc = p < P ? p : P - 1;  // groups past the end repeat the last pixel
     const bool is_dot = dot < n;
-
-    // x_u = C_gd V
-    double xu = 0.0;
-    for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * V[pc * g + j];
-    if (!is_dot) xu = 0.0;
-    // analytic minimum: open x = x_u; closed adds (N_hat - 1^T x_u) C_dd 1 / (1^T C_dd 1)
-    double x0 = xu;
-    if (CLOSED) {
-        const double lam = ((double)dr->nhat - group_dsum<NM>(xu)) / one_c;
-        x0 = is_dot ? xu + lam * sc[dot] : 0.0;
-    }
-    double x = x0;
-    int flags = 0;
-    uint32_t W = group_ballot<NM>(is_dot && x0 < 0.0);
-    if (CLOSED && dr->nhat == 0) {
-        // x = 0 is the only admissible point of a closed empty array
-        flags = W ? 1 : 0;
-        x = 0.0;
-        W = 0;
-    }
-    if (W) {
-        const double tol = 1e-13 * group_dmax<NM>(fmax(1.0, fabs(xu)));
-        double r[NM], v = x0;
-        uint32_t done = 0;
-        bool settled = false;
-        for (int round = 0; round < 4 * NM + 4; ++round) {
-            if (done == 0) {
+    double xu = 0.0, x = 0.0;
+    int n0 = 0, k = -1, flags = 0, cflags = 0;
+    uint32_t fm = 0;
+    if (!pixel_wave) {
+        // the inverse is the block's critical path: its wave issues first
+        __builtin_amdgcn_s_setprio(3);
+        prep_inverse_wave(sCdd, n, sA, red);
+        __builtin_amdgcn_s_setprio(0);
+    } else {
+        // x_u = C_gd V
+        for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * V[pc * g + j];
+        if (!is_dot) xu = 0.0;
+        // analytic minimum: open x = x_u; closed adds (N_hat - 1^T x_u) C_dd 1 / (1^T C_dd 1)
+        double x0 = xu;
+        if (CLOSED) {
+            const double lam = ((double)dr->nhat - group_dsum<NM>(xu)) / one_c;
+            x0 = is_dot ? xu + lam * sc[dot] : 0.0;
+        }
+        x = x0;
+        uint32_t W = group_ballot<NM>(is_dot && x0 < 0.0);
+        if (CLOSED && dr->nhat == 0) {
+            // x = 0 is the only admissible point of a closed empty array
+            flags = W ? 1 : 0;
+            x = 0.0;
+            W = 0;
+        }
+        if (W) {
+            const double tol = 1e-13 * group_dmax<NM>(fmax(1.0, fabs(xu)));
+            const double rone_c = CLOSED ? 1.0 / one_c : 0.0;
+            double r[NM], v = x0;
+            uint32_t done = 0;
+            bool settled = false;
+            for (int round = 0; round < 4 * NM + 4; ++round) {
+                if (done == 0) {
+                    // row `dot` of K (symmetric), identity beyond n, read
+                    // afresh (the fence keeps the compiler from holding all
+                    // of K in registers across the loop)
+                    __asm__ volatile("" ::: "memory");
 #pragma unroll
-                for (int q = 0; q < NM; ++q) r[q] = sK[q * NM + dot];
-                v = x0;
+                    for (int q = 0; q < NM; ++q) {
+                        double kv = (q == dot) ? 1.0 : 0.0;
+                        if (q < n && is_dot) {
+                            kv = sCdd[q * kMaxDot + dot];
+                            if (CLOSED) kv -= (sc[q] * sc[dot]) * rone_c;
+                        }
+                        r[q] = kv;
+                    }
+                    v = x0;
+                }
+                for (uint32_t todo = W & ~done; todo; todo &= todo - 1)
+                    gj_pivot<NM>(r, v, __ffs(todo) - 1, dot, base);
+                done = W;
+                const bool in_w = W >> dot & 1u;
+                x = in_w ? 0.0 : v;
+                const bool keep = is_dot && (in_w ? (-v > -tol) : (v < -tol));
+                const uint32_t Wn = group_ballot<NM>(keep);
+                if (Wn == W) { settled = true; break; }
+                if (W & ~Wn) done = 0;  // a dot leaves the active set: eliminate afresh
+                W = Wn;
             }
-            for (uint32_t todo = W & ~done; todo; todo &= todo - 1)
-                gj_pivot<NM>(r, v, __ffs(todo) - 1, dot, base);
-            done = W;
-            const bool in_w = W >> dot & 1u;
-            x = in_w ? 0.0 : v;
-            const bool keep = is_dot && (in_w ? (-v > -tol) : (v < -tol));
-            const uint32_t Wn = group_ballot<NM>(keep);
-            if (Wn == W) { settled = true; break; }
-            if (W & ~Wn) done = 0;  // a dot leaves the active set: eliminate afresh
-            W = Wn;
+            x = is_dot ? fmax(x, 0.0) : 0.0;
+            flags = settled ? 1 : 3;
         }
-        x = is_dot ? fmax(x, 0.0) : 0.0;
-        flags = settled ? 1 : 3;
-    }
 
-    // candidate set (Sec. 3.2): base n0, free dots, closed: k raised free dots
-    double t = dr->t;
-    int n0 = 0, k = -1, cflags = 0;
-    bool freed = false;
-    for (int iter = 0; iter < 80; ++iter) {
-        // the box starts at floor(x* + 1e-9): a continuous minimum on an
-        // integer keeps that integer as its floor whatever its last bit
-        const double f = floor(x + 1e-9);
-        const double fr = x - f;
-        freed = is_dot && ((t >= 1.0) || (fabs(fr - 0.5) <= 0.5 * t));
-        n0 = is_dot ? (int)f + ((!freed && fr > 0.5) ? 1 : 0) : 0;
-        if (!CLOSED) break;
-        const int sum0 = group_isum<NM>(n0);
-        const int nfree = __popc(group_ballot<NM>(freed));
-        const int need = dr->nhat - sum0;
-        if (need >= 0 && need <= nfree) { k = need; break; }
-        if (t >= 1.0) {  // |sum x* - N_hat| < 1 makes this unreachable
-            k = need < 0 ? 0 : nfree;
-            cflags |= 2;
-            break;
+        // candidate set (Sec. 3.2): base n0, free dots, closed: k raised free dots
+        double t = dr->t;
+        bool freed = false;
+        for (int iter = 0; iter < 80; ++iter) {
+            // the box starts at floor(x* + 1e-9): a continuous minimum on an
+            // integer keeps that integer as its floor whatever its last bit
+            const double f = floor(x + 1e-9);
+            const double fr = x - f;
+            freed = is_dot && ((t >= 1.0) || (fabs(fr - 0.5) <= 0.5 * t));
+            n0 = is_dot ? (int)f + ((!freed && fr > 0.5) ? 1 : 0) : 0;
+            if (!CLOSED) break;
+            const int sum0 = group_isum<NM>(n0);
+            const int nfree = __popc(group_ballot<NM>(freed));
+            const int need = dr->nhat - sum0;
+            if (need >= 0 && need <= nfree) { k = need; break; }
+            if (t >= 1.0) {  // |sum x* - N_hat| < 1 makes this unreachable
+                k = need < 0 ? 0 : nfree;
+                cflags |= 2;
+                break;
+            }
+            t = (t > 0.0) ? fmin(1.0, 2.0 * t) : 1.0;
+            cflags |= 4;
         }
-        t = (t > 0.0) ? fmin(1.0, 2.0 * t) : 1.0;
-        cflags |= 4;
+        fm = group_ballot<NM>(freed);
     }
-    const uint32_t fm = group_ballot<NM>(freed);
+    __syncthreads();  // A from wave 0
 
-    // g0 = A (n0 - x_u) and U(n0) = 1/2 (n0 - x_u)^T g0 (Eq. free_energy)
-    const double z = is_dot ? (double)n0 - xu : 0.0;
-    double g0 = 0.0;
+    if (pixel_wave) {
+        // g0 = A (n0 - x_u) and U(n0) = 1/2 (n0 - x_u)^T g0 (Eq. free_energy)
+        const double z = is_dot ? (double)n0 - xu : 0.0;
+        double g0 = 0.0;
 #pragma unroll
-    for (int q = 0; q < NM; ++q) g0 += sA[q * kMaxDot + dot] * __shfl(z, base + q, kWave);
-    const double u0 = 0.5 * group_dsum<NM>(z * g0);
+        for (int q = 0; q < NM; ++q) g0 += sA[q * kMaxDot + dot] * __shfl(z, base + q, kWave);
+        const double u0 = 0.5 * group_dsum<NM>(z * g0);
 
-    if (p < P) {
-        PixRec *o = pr + p;
-        for (int q = dot; q < kMaxDot; q += NM) {
-            o->g0[q] = (q < NM) ? g0 : 0.0;
-            o->n0[q] = (int16_t)((q < NM) ? n0 : 0);
+        if (p < P) {
+            PixRec *o = pr + p;
+            for (int q = dot; q < kMaxDot; q += NM) {
+                o->g0[q] = (q < NM) ? g0 : 0.0;
+                o->n0[q] = (int16_t)((q < NM) ? n0 : 0);
+            }
+            if (dot == 0) {
+                o->u0 = u0;
+                o->free = fm;
+                o->k = k;
+                o->flags = flags | cflags;
+                o->pad = 0;
+                if (flags_out) flags_out[p] = flags | (cflags & 4);
+                if (cflags & 4) atomicAdd(&cnt[2], 1);
+                if (flags & 1) atomicAdd(&cnt[1], 1);
+                if (flags & 2) atomicAdd(&cnt[3], 1);
+                atomicAdd(&cnt[0], 1);
+            }
+            if (x_out && is_dot) x_out[p * n + dot] = x;
         }
-        if (dot == 0) {
-            o->u0 = u0;
-            o->free = fm;
-            o->k = k;
-            o->flags = flags | cflags;
-            o->pad = 0;
-            if (flags_out) flags_out[p] = flags | (cflags & 4);
-            if (cflags & 4) atomicAdd(&cnt[2], 1);
-            if (flags & 1) atomicAdd(&cnt[1], 1);
-            if (flags & 2) atomicAdd(&cnt[3], 1);
-            atomicAdd(&cnt[0], 1);
-        }
-        if (x_out && is_dot) x_out[p * n + dot] = x;
     }
     // per-block counts with plain stores (the host sums them): the counters
     // of this call are cleared by block 0 concurrently, so no atomics here
@@ -309,7 +344,7 @@ __global__ __launch_bounds__(256) void k_setup(DiagRec *__restrict__ dr,
 int64_t setup_blocks(int64_t P, int n_dot)
 {
     int64_t b = 0;
-    QA_DISPATCH_NM(n_dot, b = (P * NM_ + 255) / 256);
+    QA_DISPATCH_NM(n_dot, b = (P * NM_ + kSetupPixThreads - 1) / kSetupPixThreads);
     return b < 1 ? 1 : b;
 }
 
@@ -317,7 +352,7 @@ hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int
                         int32_t *bstats, int n_dot, bool closed, hipStream_t s, double *x_out,
                         int32_t *flags_out)
 {
-    const dim3 grid((unsigned)setup_blocks(P, n_dot)), block(256);
+    const dim3 grid((unsigned)setup_blocks(P, n_dot)), block(kSetupThreads);
     if (closed)
         QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>), grid, block, 0, s, dr, V,
                                                  P, pr, counters, bstats, x_out, flags_out));
