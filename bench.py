@@ -344,6 +344,36 @@ def run_extras(qa, W, torch, d, V, out, args):
                        "ms_per_diagram": round(1e3 * wall / steps, 4)}
         log("%s: %s" % (name, small[name]))
     res["small_workloads"] = small
+    # the paper's own benchmark (Sec. 7): random uniform capacitances in
+    # Maxwell form, 100 x 100 random gate voltages, N = 1..16, open and closed
+    # with as many carriers as dots; and the threshold sweep of its second
+    # figure.  ms per diagram, headline form for open N >= 9, FP64 elsewhere.
+    replica = {}
+    for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
+        entry = {}
+        for closed in (False, True):
+            dg = W.paper_replica(n, seed=500 + n, closed=closed)
+            Vr = torch.as_tensor(dg.V, device="cuda")
+            o = torch.empty((dg.P, dg.n_dot), dtype=torch.int32, device="cuda")
+            wall = timed_calls(direct_gs(qa, dg, Vr, o, args.precision, torch), 10, 2, torch)
+            entry["closed_ms" if closed else "open_ms"] = round(1e3 * wall / 10, 4)
+        replica["N=%d" % n] = entry
+    log("paper benchmark replica (ms per 100x100 diagram): %s" % replica)
+    sweep = {}
+    for n in (8, 12, 16):
+        for closed in (False, True):
+            for t in (1.0, 2 / 3, 1 / 2, 1 / 3):
+                dg = W.paper_replica(n, seed=500 + n, closed=closed)
+                dg.t = t
+                Vr = torch.as_tensor(dg.V, device="cuda")
+                o = torch.empty((dg.P, dg.n_dot), dtype=torch.int32, device="cuda")
+                wall = timed_calls(direct_gs(qa, dg, Vr, o, args.precision, torch), 10, 2, torch)
+                sweep["N=%d %s t=%.3f" % (n, "closed" if closed else "open", t)] = round(
+                    1e3 * wall / 10, 4)
+    log("threshold sweep (ms per diagram): %s" % sweep)
+    res["paper_benchmark_replica"] = {"ms_per_diagram": replica, "threshold_sweep_ms": sweep,
+                                      "inputs": "random_maxwell capacitances, V ~ U[-1, 2]^N, "
+                                                "seed 500 + N"}
     # adjoint: 2x4 array + sensor dot, kT = 0.02, forward + backward
     a = W.adjoint_case(400)
     Va = torch.as_tensor(a.V, device="cuda")
@@ -358,9 +388,25 @@ def run_extras(qa, W, torch, d, V, out, args):
         nb, saved = qa.soft_charge(cdd8, cgd8, Va, a.kT)
         qa.soft_charge_backward(cdd8, cgd8, Va, a.kT, gb, saved)
     wp = timed_calls(fwdbwd_py, steps, 3, torch)
+    # the whole training step through torch autograd: SoftCharge over the
+    # array block, the sensor's linear response (row 8 of the 9 x 9 inverse)
+    # and a mean-square loss, backward to C_dd, C_gd and V (target: zeros;
+    # the values do not matter for the timing)
+    C9 = torch.tensor(a.cdd, dtype=torch.float64, device="cuda", requires_grad=True)
+    G9 = torch.tensor(a.cgd, dtype=torch.float64, device="cuda", requires_grad=True)
+    Vg = Va.clone().requires_grad_(True)
+
+    def train_step():
+        nb = qa.SoftCharge.apply(C9[:8, :8], G9[:8, :], Vg, a.kT)
+        S = nb @ torch.linalg.inv(C9)[8, :8]
+        loss = (S * S).mean()
+        C9.grad = G9.grad = Vg.grad = None
+        loss.backward()
+    wg = timed_calls(train_step, steps, 3, torch)
     res["adjoint_8dot_sensor"] = {"fwd_ms": round(1e3 * wf / steps, 4),
                                   "fwd_bwd_ms_per_diagram": round(1e3 * wb / steps, 4),
                                   "fwd_bwd_ms_python_wrappers": round(1e3 * wp / steps, 4),
+                                  "train_step_ms_torch_autograd": round(1e3 * wg / steps, 4),
                                   "pixels": int(Va.shape[0])}
     log("adjoint: %s" % res["adjoint_8dot_sensor"])
     # ragged dataset batch: 4096 diagrams of 2..8 dots, 64 x 64 pixels each

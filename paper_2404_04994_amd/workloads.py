@@ -284,3 +284,18 @@ def random_maxwell(n_dot: int, seed: int, n_gate: int | None = None):
     cdd = maxwell[:n_dot, :n_dot].copy()
     cgd = -maxwell[:n_dot, n_dot:].copy()
     return cdd, cgd
+
+
+def paper_replica(n_dot: int, seed: int = 500, npix: int = 100, closed: bool = False,
+                  vmin: float = -1.0, vmax: float = 2.0) -> Diagram:
+    """The paper's benchmark (Sec. 7): random capacitances (``random_maxwell``,
+    one gate per dot) and npix x npix gate-voltage configurations drawn
+    uniformly in [vmin, vmax]^G (the paper gives no range; negative voltages
+    make some analytic minima infeasible, so the QP runs too); closed arrays
+    hold as many carriers as dots."""
+    cdd, cgd = random_maxwell(n_dot, seed)
+    rng = np.random.default_rng(seed + 7)
+    V = rng.uniform(vmin, vmax, (npix * npix, cgd.shape[1]))
+    return Diagram(cdd, cgd, V, closed=closed, nhat=n_dot if closed else 0,
+                   meta=dict(workload="paper benchmark replica", seed=seed))
+
