@@ -221,6 +221,28 @@ void qa_graphs_enable(int on);
 void qa_timing_reset(void *hip_stream);
 qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out);
 
+/* Optimal gate voltages (Sec. 5.3, App. H): the V that minimises the free
+ * energy of the fixed dot charges q, i.e. the least-squares solution of
+ * R q = R C_gd V with R^T R = C_dd^{-1} (Cholesky), V = (R C_gd)^+ R q
+ * (Moore-Penrose pseudo-inverse: exact when C_gd is square and invertible,
+ * minimum-norm when there are more gates than dots, least squares when
+ * fewer).  Host FP64; no device work.
+ *   q     : host, N doubles (charges in units of e, holes positive).
+ *   v_out : host, G doubles.
+ * Uses n_dot, n_gate, cdd, cgd of prob (validated as for every entry point;
+ * mode, kT, threshold and precision are ignored beyond validation). */
+qa_status qa_optimal_gate_voltages(const qa_problem *prob, const double *q, double *v_out);
+
+/* Virtual-gate matrix (Sec. 5.3, App. I): alpha = (C_dd^{-1} C_gd)^+, G x N
+ * row-major into alpha_out (host).  The dot potentials move by
+ * C_dd^{-1} C_gd dV (Eq. for the potential), so column i of alpha is the
+ * gate-voltage change that moves dot i's potential by one unit and leaves
+ * the others (exactly when C_dd^{-1} C_gd has full row rank, otherwise in
+ * the least-squares sense with minimum norm).  Host FP64; no device work.
+ * The paper's transposed product C_gd C_dd^{-1} is defined only for square
+ * C_gd; this form is its general reading. */
+qa_status qa_virtual_gate_matrix(const qa_problem *prob, double *alpha_out);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char *qa_last_error(void);
 

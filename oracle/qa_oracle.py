@@ -302,3 +302,28 @@ def exact_soft(cdd, cgd, V, closed=False, nhat=0, kT=0.01):
     lib().orc_exact_soft(P, n, g, _d(cdd), _d(cgd), _d(V), int(closed), int(nhat), float(kT),
                          _d(nbar), _l(cnt))
     return nbar, cnt
+
+
+# ---------------------------------------------------------------------------
+# Analytic utilities (Sec. 5.3), numpy FP64 with library primitives
+# ---------------------------------------------------------------------------
+
+def optimal_gate_voltages(cdd, cgd, q):
+    """App. H: minimise F over the gate voltages for fixed charges q.  With
+    the Cholesky factor L of C_dd (C_dd = L L^T), R = L^-1 satisfies
+    R^T R = C_dd^-1 and F = 1/2 |R (q - C_gd V)|^2, a linear least-squares
+    problem solved by the pseudo-inverse: V = (R C_gd)^+ R q."""
+    cdd = np.asarray(cdd, np.float64)
+    cgd = np.asarray(cgd, np.float64)
+    L = np.linalg.cholesky(cdd)
+    R = np.linalg.inv(L)
+    return np.linalg.pinv(R @ cgd) @ (R @ np.asarray(q, np.float64))
+
+
+def virtual_gate_matrix(cdd, cgd):
+    """App. I: the dot potentials move by C_dd^-1 C_gd dV (Eq. for the
+    potential); alpha = (C_dd^-1 C_gd)^+ (G x N), column i the gate change that
+    moves dot i's potential by one unit."""
+    cdd = np.asarray(cdd, np.float64)
+    cgd = np.asarray(cgd, np.float64)
+    return np.linalg.pinv(np.linalg.solve(cdd, cgd))

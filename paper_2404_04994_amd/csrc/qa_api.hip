@@ -776,6 +776,170 @@ void qa_release(void *hip_stream)
     delete w;
 }
 
+// ---------------------------------------------------------------------------
+// Host FP64 utilities: optimal gate voltages and the virtual-gate matrix
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// Moore-Penrose pseudo-inverse of the m x n row-major matrix M into X
+// (n x m, row-major) by a one-sided Jacobi SVD (Hestenes): the columns of a
+// working copy are rotated pairwise until mutually orthogonal, so that
+// W = M V has orthogonal columns w_j = sigma_j u_j; then M+ = V S+ U^T.
+// Singular values below 1e-15 sigma_max count as zero.  m, n <= 32.
+void pinv(int m, int n, const double *M, double *X)
+{
+    if (m < n) {  // fat: pinv(M) = pinv(M^T)^T
+        double T[32 * 32], Y[32 * 32];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) T[j * m + i] = M[i * n + j];
+        pinv(n, m, T, Y);  // Y is m x n
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) X[j * m + i] = Y[i * n + j];
+        return;
+    }
+    double W[32 * 32], V[32 * 32];
+    for (int i = 0; i < m * n; ++i) W[i] = M[i];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double a = 0.0, b = 0.0, c = 0.0;
+                for (int i = 0; i < m; ++i) {
+                    a += W[i * n + p] * W[i * n + p];
+                    b += W[i * n + q] * W[i * n + q];
+                    c += W[i * n + p] * W[i * n + q];
+                }
+                if (c == 0.0 || std::fabs(c) <= 1e-17 * std::sqrt(a * b)) continue;
+                off = std::fmax(off, std::fabs(c) / std::sqrt(a * b));
+                // rotation that zeroes the (p, q) entry of W^T W
+                const double zeta = (b - a) / (2.0 * c);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) /
+                                 (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = cs * t;
+                for (int i = 0; i < m; ++i) {
+                    const double wp = W[i * n + p], wq = W[i * n + q];
+                    W[i * n + p] = cs * wp - sn * wq;
+                    W[i * n + q] = sn * wp + cs * wq;
+                }
+                for (int i = 0; i < n; ++i) {
+                    const double vp = V[i * n + p], vq = V[i * n + q];
+                    V[i * n + p] = cs * vp - sn * vq;
+                    V[i * n + q] = sn * vp + cs * vq;
+                }
+            }
+        if (off < 1e-15) break;
+    }
+    double sig[32], smax = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s2 = 0.0;
+        for (int i = 0; i < m; ++i) s2 += W[i * n + j] * W[i * n + j];
+        sig[j] = std::sqrt(s2);
+        smax = std::fmax(smax, sig[j]);
+    }
+    // X = V S+ U^T with u_j = w_j / sigma_j, so column j contributes
+    // v_j w_j^T / sigma_j^2
+    for (int i = 0; i < n * m; ++i) X[i] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        if (!(sig[j] > 1e-15 * smax)) continue;
+        const double f = 1.0 / (sig[j] * sig[j]);
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < m; ++c) X[r * m + c] += V[r * n + j] * W[c * n + j] * f;
+    }
+}
+
+// Cholesky factor L of C_dd (C_dd = L L^T) and R = L^{-1}, so that
+// R^T R = C_dd^{-1}; A = C_dd^{-1}.  The problem has been validated.
+void chol_inverse(int n, const double *C, double *R, double *A)
+{
+    double L[QA_MAX_DOT * QA_MAX_DOT] = {0};
+    for (int j = 0; j < n; ++j) {
+        double d = C[j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        L[j * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double s = C[i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = s / L[j * n + j];
+        }
+    }
+    // R = L^{-1} (lower triangular), column by column
+    for (int i = 0; i < n * n; ++i) R[i] = 0.0;
+    for (int c = 0; c < n; ++c) {
+        for (int i = c; i < n; ++i) {
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) s -= L[i * n + k] * R[k * n + c];
+            R[i * n + c] = s / L[i * n + i];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += R[k * n + i] * R[k * n + j];
+            A[i * n + j] = s;
+        }
+}
+
+}  // namespace
+
+extern "C" {
+
+qa_status qa_optimal_gate_voltages(const qa_problem *prob, const double *q, double *v_out)
+{
+    g_err.clear();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    if (!q || !v_out) return fail(QA_E_NULL, "q or v_out is NULL");
+    const int n = prob->n_dot, g = prob->n_gate;
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(q[i])) return fail(QA_E_RANGE, "q[%d] is not finite", i);
+    double R[QA_MAX_DOT * QA_MAX_DOT], A[QA_MAX_DOT * QA_MAX_DOT];
+    chol_inverse(n, prob->cdd, R, A);
+    // minimise |R q - R C_gd v|_2: v = (R C_gd)+ R q
+    double M[QA_MAX_DOT * QA_MAX_GATE], X[QA_MAX_GATE * QA_MAX_DOT], rq[QA_MAX_DOT];
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += R[i * n + k] * q[k];
+        rq[i] = s;
+        for (int j = 0; j < g; ++j) {
+            double t = 0.0;
+            for (int k = 0; k < n; ++k) t += R[i * n + k] * prob->cgd[k * g + j];
+            M[i * g + j] = t;
+        }
+    }
+    pinv(n, g, M, X);
+    for (int j = 0; j < g; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += X[j * n + i] * rq[i];
+        v_out[j] = s;
+    }
+    return QA_OK;
+}
+
+qa_status qa_virtual_gate_matrix(const qa_problem *prob, double *alpha_out)
+{
+    g_err.clear();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    if (!alpha_out) return fail(QA_E_NULL, "alpha_out is NULL");
+    const int n = prob->n_dot, g = prob->n_gate;
+    double R[QA_MAX_DOT * QA_MAX_DOT], A[QA_MAX_DOT * QA_MAX_DOT];
+    chol_inverse(n, prob->cdd, R, A);
+    // the dot potentials move by A C_gd dV; alpha = (A C_gd)+ (G x N)
+    double M[QA_MAX_DOT * QA_MAX_GATE];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < g; ++j) {
+            double t = 0.0;
+            for (int k = 0; k < n; ++k) t += A[i * n + k] * prob->cgd[k * g + j];
+            M[i * g + j] = t;
+        }
+    pinv(n, g, M, alpha_out);
+    return QA_OK;
+}
+
 const char *qa_version(void) { return "qarray-mi355x 0.1 (gfx950)"; }
 
 }  // extern "C"

@@ -75,6 +75,10 @@ def load():
         lib.qa_timing_reset.argtypes = [vp]
         lib.qa_timing_sum.argtypes = [vp, C.POINTER(C.c_double), i64p]
         lib.qa_timing_sum.restype = C.c_int
+        lib.qa_optimal_gate_voltages.argtypes = [pb, vp, vp]
+        lib.qa_optimal_gate_voltages.restype = C.c_int
+        lib.qa_virtual_gate_matrix.argtypes = [pb, vp]
+        lib.qa_virtual_gate_matrix.restype = C.c_int
         for f in ("qa_ground_state", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward",
                   "qa_ground_state_batched"):
             getattr(lib, f).restype = C.c_int
@@ -271,6 +275,26 @@ class Batch:
         o, k = int(self.out_offsets[d]), dg.P * dg.n_dot
         return (self.n[o:o + k].view(dg.P, dg.n_dot).cpu().numpy(),
                 self.nbar[o:o + k].view(dg.P, dg.n_dot).cpu().numpy())
+
+
+def optimal_gate_voltages(cdd, cgd, q):
+    """Gate voltages minimising the free energy of charges q (host FP64)."""
+    pb, keep = make_problem(cdd, cgd)
+    qh = np.ascontiguousarray(np.asarray(q, np.float64).ravel())
+    v = np.empty(pb.n_gate, np.float64)
+    _check(load().qa_optimal_gate_voltages(C.byref(pb), C.c_void_p(qh.ctypes.data),
+                                           C.c_void_p(v.ctypes.data)))
+    del keep
+    return v
+
+
+def virtual_gate_matrix(cdd, cgd):
+    """alpha = (C_dd^-1 C_gd)^+ (G x N, host FP64)."""
+    pb, keep = make_problem(cdd, cgd)
+    a = np.empty((pb.n_gate, pb.n_dot), np.float64)
+    _check(load().qa_virtual_gate_matrix(C.byref(pb), C.c_void_p(a.ctypes.data)))
+    del keep
+    return a
 
 
 def graphs_enable(on: bool = True):

@@ -134,6 +134,20 @@ def test_paper_benchmark_replica(qa, oracle, n):
         check_gs(qa, oracle, d.cdd, d.cgd, d.V[:200], closed=True, nhat=n)
 
 
+def test_optimal_gate_voltages_give_their_charge_state(qa, oracle):
+    """At the optimal gate voltages of an integer charge state (App. H) with
+    a square invertible C_gd, x_u equals the charges, so the ground state is
+    that charge state exactly (U = 0 there and positive elsewhere)."""
+    rng = np.random.default_rng(77)
+    for n in (2, 4, 9, 16):
+        cdd, cgd = W.random_maxwell(n, 600 + n)
+        Q = rng.integers(0, 5, (64, n)).astype(np.float64)
+        V = np.stack([qa.optimal_gate_voltages(cdd, cgd, q) for q in Q])
+        for prec in (("fp64", "bf16x3") if n >= 9 else ("fp64",)):
+            got = qa.ground_state(cdd, cgd, torch.as_tensor(V).cuda(), precision=prec)
+            assert (got.cpu().numpy() == Q.astype(np.int32)).all(), (n, prec)
+
+
 def test_worked_example(qa, oracle):
     d = W.paper_example()
     check_gs(qa, oracle, d.cdd, d.cgd, d.V)
