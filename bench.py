@@ -409,6 +409,27 @@ def run_extras(qa, W, torch, d, V, out, args):
                                   "train_step_ms_torch_autograd": round(1e3 * wg / steps, 4),
                                   "pixels": int(Va.shape[0])}
     log("adjoint: %s" % res["adjoint_8dot_sensor"])
+    # charge-sensed diagram (Sec. 5.1): the 8-dot array's ground state, then
+    # the sensor dot's response with white, 1/f and telegraph noise (draws
+    # made on the GPU once, outside the timed region)
+    Vs = Va.clone()
+    Vs[:, 8] = torch.linspace(0.0, 2.5, Vs.shape[0], dtype=torch.float64, device="cuda")
+    n_arr = torch.empty((Vs.shape[0], 8), dtype=torch.int32, device="cuda")
+    gs8 = direct_gs(qa, W.Diagram(cdd8, cgd8, a.V), Vs, n_arr, "fp64", torch)
+    draws = qa.sensor_noise(Vs.shape[0], 1, 8,
+                            generator=torch.Generator(device="cuda").manual_seed(9))
+
+    def sensed():
+        gs8()
+        qa.sensor_response(a.cdd, a.cgd, Vs, 1, n_arr, 0.05, white=0.01, pink=0.01,
+                           pink_octaves=8, jump=0.05, jump_rate=0.001, noise=draws)
+    ws = timed_calls(sensed, steps, 3, torch)
+    res["charge_sensed_8dot"] = {"ms_per_diagram": round(1e3 * ws / steps, 4),
+                                 "pixels_per_s": round(Vs.shape[0] * steps / ws, 1),
+                                 "pixels": int(Vs.shape[0]),
+                                 "what": "array ground state + sensor charge, potential, "
+                                         "Lorentzian response, white + 1/f + telegraph noise"}
+    log("charge-sensed diagram: %s" % res["charge_sensed_8dot"])
     # ragged dataset batch: 4096 diagrams of 2..8 dots, 64 x 64 pixels each
     if args.batch_diagrams > 0:
         t0 = time.perf_counter()

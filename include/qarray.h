@@ -221,6 +221,51 @@ void qa_graphs_enable(int on);
 void qa_timing_reset(void *hip_stream);
 qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out);
 
+/* Charge sensors (Sec. 5.1).  The problem's last n_sensor dots are sensor
+ * dots (prob: the whole system, n_dot = N_array + n_sensor).  The array
+ * dots' charges are given: their ground state or softargmin computed by the
+ * caller with the array block of C_dd (first N_array rows and columns) and
+ * of C_gd (first N_array rows, every gate), i.e. the sensors left out but
+ * the sensor gates' cross-talk kept.  Per pixel, with those charges fixed,
+ * the sensors take the charges that minimise the electrostatic energy of
+ * the whole system (the floor/ceil box around their continuous minimum,
+ * clipped at zero; exact for one sensor), their potentials follow the
+ * potential equation v = C_dd^{-1} (n - C_gd V), and the response of sensor
+ * s is P(v_s + A_ss/2) + P(-v_s + A_ss/2) (A = C_dd^{-1}; the second term
+ * only when the sensor is occupied): the energy to add or to remove one
+ * carrier, each zero at a Coulomb-peak condition, under the peak profile P
+ * (Lorentzian 1/(1 + (x/gamma)^2) or Gaussian exp(-x^2/(2 gamma^2)), peak 1).
+ * Noise is added from draws the caller passes (noise_dev, device FP64):
+ *   [0, P*S)           white: standard-normal, pixel-major (p * S + s)
+ *   then, per sensor s and octave k < pink_octaves, ceil(P / 2^k)
+ *                      standard-normal draws: 1/f noise by the
+ *                      Voss-McCartney sum over the octaves / sqrt(K)
+ *   then [.., + P*S)   uniform [0, 1) draws: telegraph jumps, the state
+ *                      flips where a draw is below jump_rate (pixel order)
+ * qa_sensor_noise_len(P, S, K) gives the total; noise_dev may be NULL when
+ * white, pink and jump are all 0.
+ *   n_array_dev     : device, P x N_array int32 (ground state), or NULL and
+ *   nbar_array_dev  : device, P x N_array FP64 (softargmin).
+ *   signal_dev      : device, P x n_sensor FP64. */
+typedef enum { QA_SENSOR_LORENTZIAN = 0, QA_SENSOR_GAUSSIAN = 1 } qa_sensor_shape;
+typedef struct {
+    int32_t n_sensor;      /* 1..4 */
+    int32_t shape;         /* qa_sensor_shape */
+    double gamma;          /* peak width, > 0 (energy units of U) */
+    double white;          /* white-noise amplitude, >= 0 */
+    double pink;           /* 1/f-noise amplitude, >= 0 */
+    int32_t pink_octaves;  /* K, 1..40 when pink > 0 */
+    int32_t reserved;
+    double jump;           /* telegraph-jump amplitude, >= 0 */
+    double jump_rate;      /* flip probability per sample, [0, 1] */
+} qa_sensor;
+
+size_t qa_sensor_noise_len(int64_t P, int32_t n_sensor, int32_t pink_octaves);
+
+qa_status qa_sensor_response(const qa_problem *prob, const qa_sensor *sensor, const double *V_dev,
+                             int64_t P, const int32_t *n_array_dev, const double *nbar_array_dev,
+                             const double *noise_dev, double *signal_dev, void *hip_stream);
+
 /* Optimal gate voltages (Sec. 5.3, App. H): the V that minimises the free
  * energy of the fixed dot charges q, i.e. the least-squares solution of
  * R q = R C_gd V with R^T R = C_dd^{-1} (Cholesky), V = (R C_gd)^+ R q

@@ -327,3 +327,90 @@ def virtual_gate_matrix(cdd, cgd):
     cdd = np.asarray(cdd, np.float64)
     cgd = np.asarray(cgd, np.float64)
     return np.linalg.pinv(np.linalg.solve(cdd, cgd))
+
+
+# ---------------------------------------------------------------------------
+# Charge sensors (Sec. 5.1), numpy FP64
+# ---------------------------------------------------------------------------
+
+def sensor_charges_brute(cdd, cgd, V, n_array, n_sensor, span=6):
+    """The sensor dots' charges minimising U over every integer vector in a
+    box of +-span around the continuous minimum (clipped at 0), with the
+    array dots' charges held fixed (Sec. 5.1).  Brute force: every candidate
+    is scored by the full quadratic form.  Returns (P x S int64)."""
+    cdd = np.asarray(cdd, np.float64)
+    cgd = np.asarray(cgd, np.float64)
+    V = np.atleast_2d(np.asarray(V, np.float64))
+    na = np.atleast_2d(np.asarray(n_array, np.float64))
+    N = cdd.shape[0]
+    Na, S = N - n_sensor, n_sensor
+    A = np.linalg.inv(cdd)
+    P = V.shape[0]
+    out = np.zeros((P, S), np.int64)
+    grids = np.array(np.meshgrid(*[np.arange(-span, span + 1)] * S, indexing="ij")).reshape(S, -1).T
+    for p in range(P):
+        xu = cgd @ V[p]
+        za = na[p] - xu[:Na]
+        # continuous minimum over the sensor charges (unconstrained)
+        xs = xu[Na:] - np.linalg.solve(A[Na:, Na:], A[Na:, :Na] @ za)
+        base = np.floor(np.maximum(xs, 0.0)).astype(np.int64)
+        best, bn = np.inf, None
+        for d in grids:
+            ns = base + d
+            if (ns < 0).any():
+                continue
+            z = np.concatenate([za, ns - xu[Na:]])
+            e = 0.5 * z @ A @ z
+            # ties to the lexicographically smallest sensor charge vector
+            if e < best or (e == best and tuple(ns) < tuple(bn)):
+                best, bn = e, ns
+        out[p] = bn
+    return out
+
+
+def sensor_signal(cdd, cgd, V, n_array, n_sensor, gamma, shape="lorentzian", n_sens=None):
+    """Sensor response (Sec. 5.1): with the array charges fixed and the
+    sensor charges at their minimum, the sensor potentials follow Eq. for the
+    potential, v = C_dd^-1 (n - C_gd V); adding a carrier to sensor s costs
+    v_s + A_ss / 2 and removing one -v_s + A_ss / 2 (zero at the two nearest
+    Coulomb-peak conditions), and the response is the peak profile of each
+    (Lorentzian 1 / (1 + (x / gamma)^2) or Gaussian exp(-x^2 / (2 gamma^2)))
+    summed, the removal term only when the sensor holds a carrier.
+    Returns (P x S)."""
+    cdd = np.asarray(cdd, np.float64)
+    cgd = np.asarray(cgd, np.float64)
+    V = np.atleast_2d(np.asarray(V, np.float64))
+    na = np.atleast_2d(np.asarray(n_array, np.float64))
+    N = cdd.shape[0]
+    Na = N - n_sensor
+    A = np.linalg.inv(cdd)
+    if n_sens is None:
+        n_sens = sensor_charges_brute(cdd, cgd, V, na, n_sensor)
+    xu = V @ cgd.T
+    n = np.concatenate([na, n_sens.astype(np.float64)], axis=1)
+    v = (n - xu) @ A.T
+    diag = np.diag(A)[Na:]
+    vs = v[:, Na:]
+    prof = (lambda x: 1.0 / (1.0 + (x / gamma) ** 2)) if shape == "lorentzian" else \
+        (lambda x: np.exp(-x * x / (2.0 * gamma * gamma)))
+    up = prof(vs + 0.5 * diag)
+    down = np.where(n_sens > 0, prof(-vs + 0.5 * diag), 0.0)
+    return up + down, v
+
+
+def pink_noise(draws_by_octave, P):
+    """Voss-McCartney pink (1/f) noise: K octave sources, source k holding a
+    standard-normal draw for every 2^k consecutive samples; sample t is the
+    sum of the sources' current draws over sqrt(K) (unit variance).
+    draws_by_octave[k] has ceil(P / 2^k) entries."""
+    K = len(draws_by_octave)
+    t = np.arange(P)
+    return sum(np.asarray(draws_by_octave[k])[t >> k] for k in range(K)) / np.sqrt(K)
+
+
+def telegraph_noise(u, rate):
+    """Random telegraph (sensor jump) noise: the state starts at 0 and flips
+    at sample t when the uniform draw u_t < rate; the state at t counts the
+    flips up to and including t, mod 2."""
+    flips = (np.asarray(u) < rate).astype(np.int64)
+    return np.cumsum(flips) % 2

@@ -776,6 +776,66 @@ void qa_release(void *hip_stream)
     delete w;
 }
 
+size_t qa_sensor_noise_len(int64_t P, int32_t n_sensor, int32_t pink_octaves)
+{
+    if (P <= 0 || n_sensor <= 0) return 0;
+    size_t len = 2 * (size_t)P * (size_t)n_sensor;
+    for (int k = 0; k < pink_octaves; ++k)
+        len += (size_t)n_sensor * (size_t)((P + ((int64_t)1 << k) - 1) >> k);
+    return len;
+}
+
+qa_status qa_sensor_response(const qa_problem *prob, const qa_sensor *sp, const double *V_dev,
+                             int64_t P, const int32_t *n_array_dev, const double *nbar_array_dev,
+                             const double *noise_dev, double *signal_dev, void *hip_stream)
+{
+    g_err.clear();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    if (!sp) return fail(QA_E_NULL, "sensor parameters are NULL");
+    if (sp->n_sensor < 1 || sp->n_sensor > 4 || sp->n_sensor >= prob->n_dot + 1)
+        return fail(QA_E_SHAPE, "n_sensor=%d outside [1, min(4, n_dot)]", sp->n_sensor);
+    if (sp->shape != QA_SENSOR_LORENTZIAN && sp->shape != QA_SENSOR_GAUSSIAN)
+        return fail(QA_E_RANGE, "shape=%d unknown", sp->shape);
+    if (!std::isfinite(sp->gamma) || !(sp->gamma > 0.0))
+        return fail(QA_E_RANGE, "gamma=%g must be positive", sp->gamma);
+    if (!(sp->white >= 0.0) || !(sp->pink >= 0.0) || !(sp->jump >= 0.0) ||
+        !std::isfinite(sp->white) || !std::isfinite(sp->pink) || !std::isfinite(sp->jump))
+        return fail(QA_E_RANGE, "noise amplitudes must be finite and >= 0");
+    if (!(sp->jump_rate >= 0.0 && sp->jump_rate <= 1.0))
+        return fail(QA_E_RANGE, "jump_rate=%g outside [0, 1]", sp->jump_rate);
+    if (sp->pink_octaves < 0 || sp->pink_octaves > 40 || (sp->pink > 0.0 && sp->pink_octaves < 1))
+        return fail(QA_E_RANGE, "pink_octaves=%d outside [%d, 40]", sp->pink_octaves,
+                    sp->pink > 0.0 ? 1 : 0);
+    if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
+    if (P == 0) return QA_OK;
+    if (!V_dev || !signal_dev) return fail(QA_E_NULL, "V_dev or signal_dev is NULL");
+    if (prob->n_dot > sp->n_sensor && !n_array_dev && !nbar_array_dev)
+        return fail(QA_E_NULL, "the array charges (n_array_dev or nbar_array_dev) are NULL");
+    const bool noisy = sp->white > 0.0 || sp->pink > 0.0 || sp->jump > 0.0;
+    if (noisy && !noise_dev) return fail(QA_E_NULL, "noise_dev is NULL with noise switched on");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    DiagRec *dr0 = w->dr;
+    if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
+    if (w->dr != dr0) w->dr_inputs.clear();
+    if ((st = upload_diag(w, prob))) return st;
+    const int S = sp->n_sensor;
+    const double *white = (noisy && sp->white > 0.0) ? noise_dev : nullptr;
+    const double *pink = (noisy && sp->pink > 0.0) ? noise_dev + (size_t)P * S : nullptr;
+    // the layout of qa_sensor_noise_len: white, pink_octaves octaves, jumps
+    size_t pink_len = 0;
+    for (int k = 0; k < sp->pink_octaves; ++k)
+        pink_len += (size_t)S * (size_t)((P + ((int64_t)1 << k) - 1) >> k);
+    QA_HIP(launch_sensor(w->dr, S, sp->shape, sp->gamma, V_dev, P, n_array_dev,
+                         n_array_dev ? nullptr : nbar_array_dev, white, sp->white, pink, sp->pink,
+                         sp->pink > 0.0 ? sp->pink_octaves : 0, signal_dev, w->stream));
+    if (sp->jump > 0.0 && sp->jump_rate > 0.0)
+        QA_HIP(launch_sensor_jumps(P, S, noise_dev + (size_t)P * S + pink_len, sp->jump_rate,
+                                   sp->jump, signal_dev, w->stream));
+    return QA_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Host FP64 utilities: optimal gate voltages and the virtual-gate matrix
 // ---------------------------------------------------------------------------

@@ -148,6 +148,15 @@ hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P,
 hipError_t launch_soft_bwd_final(const DiagRec *dr, const double *accA, const double *accG,
                                  const double *accU, double *grad_cdd, double *grad_cgd,
                                  hipStream_t s);
+// charge-sensor response (qa_sensor.hip): the last n_sensor dots of dr are
+// sensors; array charges from n_int or n_dbl (P x (n - n_sensor)); noise
+// draws optional (NULL: none); signal P x n_sensor
+hipError_t launch_sensor(const DiagRec *dr, int n_sensor, int shape, double gamma, const double *V,
+                         int64_t P, const int32_t *n_int, const double *n_dbl,
+                         const double *white_draws, double white, const double *pink_draws,
+                         double pink, int octaves, double *signal, hipStream_t s);
+hipError_t launch_sensor_jumps(int64_t P, int n_sensor, const double *u, double rate, double amp,
+                               double *signal, hipStream_t s);
 // ragged batch (qa_batch.hip): prologue of every diagram, then one persistent
 // kernel over all 64-pixel work items
 hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *recs, int n_diag,

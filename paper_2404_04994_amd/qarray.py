@@ -75,6 +75,10 @@ def load():
         lib.qa_timing_reset.argtypes = [vp]
         lib.qa_timing_sum.argtypes = [vp, C.POINTER(C.c_double), i64p]
         lib.qa_timing_sum.restype = C.c_int
+        lib.qa_sensor_response.argtypes = [pb, C.POINTER(Sensor), vp, C.c_int64, vp, vp, vp, vp, vp]
+        lib.qa_sensor_response.restype = C.c_int
+        lib.qa_sensor_noise_len.argtypes = [C.c_int64, C.c_int32, C.c_int32]
+        lib.qa_sensor_noise_len.restype = C.c_size_t
         lib.qa_optimal_gate_voltages.argtypes = [pb, vp, vp]
         lib.qa_optimal_gate_voltages.restype = C.c_int
         lib.qa_virtual_gate_matrix.argtypes = [pb, vp]
@@ -275,6 +279,62 @@ class Batch:
         o, k = int(self.out_offsets[d]), dg.P * dg.n_dot
         return (self.n[o:o + k].view(dg.P, dg.n_dot).cpu().numpy(),
                 self.nbar[o:o + k].view(dg.P, dg.n_dot).cpu().numpy())
+
+
+class Sensor(C.Structure):
+    _fields_ = [("n_sensor", C.c_int32), ("shape", C.c_int32), ("gamma", C.c_double),
+                ("white", C.c_double), ("pink", C.c_double), ("pink_octaves", C.c_int32),
+                ("reserved", C.c_int32), ("jump", C.c_double), ("jump_rate", C.c_double)]
+
+
+SENSOR_SHAPE = {"lorentzian": 0, "gaussian": 1}
+
+
+def sensor_noise_len(P: int, n_sensor: int, pink_octaves: int = 0) -> int:
+    return int(load().qa_sensor_noise_len(P, n_sensor, pink_octaves))
+
+
+def sensor_noise(P, n_sensor, pink_octaves=0, generator=None, device="cuda"):
+    """Draws in the layout qa_sensor_response reads: standard-normal white
+    and octave draws, then uniform jump draws (torch's generator)."""
+    n = sensor_noise_len(P, n_sensor, pink_octaves)
+    buf = torch.randn(n, dtype=torch.float64, device=device, generator=generator)
+    buf[n - P * n_sensor:] = torch.rand(P * n_sensor, dtype=torch.float64, device=device,
+                                        generator=generator)
+    return buf
+
+
+def sensor_response(cdd, cgd, V, n_sensor, n_array=None, gamma=0.05, shape="lorentzian",
+                    white=0.0, pink=0.0, pink_octaves=0, jump=0.0, jump_rate=0.0, noise=None,
+                    stream=None):
+    """Charge-sensor signal (P x n_sensor, FP64 on the GPU) of the whole
+    system (the last n_sensor dots are sensors) given the array charges
+    n_array (int32 ground states or FP64 soft charges, P x N_array)."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd)
+    V = _device_V(V, pb.n_gate)
+    P = V.shape[0]
+    sp = Sensor(int(n_sensor), SENSOR_SHAPE[shape] if isinstance(shape, str) else int(shape),
+                float(gamma), float(white), float(pink), int(pink_octaves), 0, float(jump),
+                float(jump_rate))
+    n_int = n_dbl = None
+    if n_array is not None:
+        n_array = torch.as_tensor(n_array).to(V.device).contiguous()
+        if n_array.dtype == torch.int32:
+            n_int = n_array
+        else:
+            n_dbl = n_array.to(torch.float64).contiguous()
+    out = torch.empty((P, int(n_sensor)), dtype=torch.float64, device=V.device)
+    if noise is not None:
+        noise = torch.as_tensor(noise, dtype=torch.float64).to(V.device).contiguous()
+    _check(lib.qa_sensor_response(
+        C.byref(pb), C.byref(sp), C.c_void_p(V.data_ptr()), P,
+        C.c_void_p(n_int.data_ptr()) if n_int is not None else None,
+        C.c_void_p(n_dbl.data_ptr()) if n_dbl is not None else None,
+        C.c_void_p(noise.data_ptr()) if noise is not None else None,
+        C.c_void_p(out.data_ptr()), _stream(stream)))
+    del keep
+    return out
 
 
 def optimal_gate_voltages(cdd, cgd, q):
