@@ -274,7 +274,14 @@ qa_status grow_single(Workspace *w, int64_t P)
 
 bool use_matrix_cores(const qa_problem *pb)
 {
-    return pb->precision != QA_PREC_FP64 && pb->n_dot >= 9 && pb->mode == QA_OPEN;
+    return pb->precision != QA_PREC_FP64 && pb->n_dot >= 9;
+}
+
+// candidate family of the matrix-core scorer: dense box, thresholded
+// sub-box, or closed subsets
+int scorer_mode(const qa_problem *pb)
+{
+    return pb->mode == QA_CLOSED ? 2 : (pb->threshold < 1.0 ? 1 : 0);
 }
 
 // The device work of one single-diagram call on stream s (inputs already in
@@ -292,7 +299,7 @@ qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, cons
         QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else if (use_matrix_cores(pb)) {
-        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, pb->threshold < 1.0, n_out,
+        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, scorer_mode(pb), n_out,
                                  w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else {
@@ -314,7 +321,7 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
     w->bstats_used = setup_blocks(P, pb->n_dot);
     std::array<hipEvent_t, 4> *ev = timing_slot(w);
     if (ev || !g_graphs) return enqueue_single(w, w->stream, pb, V, P, n_out, nbar, saved, ev);
-    const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + 2 * pb->precision + (pb->threshold < 1.0) : 1);
+    const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + 3 * pb->precision + scorer_mode(pb) : 1);
     std::vector<int64_t> key = {pb->n_dot, pb->mode, path, P, (int64_t)(uintptr_t)V,
                                 (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
                                 (int64_t)(uintptr_t)saved, (int64_t)(uintptr_t)w->dr,

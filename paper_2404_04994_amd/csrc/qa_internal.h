@@ -131,12 +131,11 @@ hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int
 // T = 0 argmin in FP64 over the candidate set of every pixel
 hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P, int32_t *n_out,
                              int64_t *counters, int n_dot, hipStream_t s);
-// matrix-core scorer at T = 0 over the dense box, or (pruned) over the
-// sub-box of each pixel's free dots (near ties re-scored in FP64 inside the
-// kernel)
-hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
-                             bool pruned, int32_t *n_out, int64_t *counters, int n_dot,
-                             hipStream_t s);
+// matrix-core scorer at T = 0; mode 0: the dense box, 1: the sub-box of each
+// pixel's free dots (thresholded), 2: closed arrays (subsets of the free
+// dots with k raised); near ties re-scored in FP64 inside the kernel
+hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec, int mode,
+                             int32_t *n_out, int64_t *counters, int n_dot, hipStream_t s);
 hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
                            SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s);
 // adjoint partial sums into accA (kMaxDot^2), accG (kMaxDot x kMaxGate) and

@@ -65,19 +65,30 @@ constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
 #define QA_SCORER_WAVES 3
 #endif
 
-// PRUNED: the thresholded candidate set (Sec. 3.2.2), n0 + b with b a subset
-// of the pixel's free dots.  A fixed dot i gets the penalty 2^100 added to
+// MODE kDense: the floor/ceil box.  kPruned: the thresholded candidate set
+// (Sec. 3.2.2), n0 + b with b a subset of the pixel's free dots.  kClosed:
+// closed arrays (Sec. 2, constraint iii), b a subset of the free dots with
+// exactly k raised (k and the free dots from the setup, after any threshold
+// doubling); a state's popcount is popc(row bits) + popc(column bits) of its
+// tile, so each lane knows which of its four elements qualify for a tile's
+// uniform remainder k - popc(rt) - popc(ct) and sets the others to +inf
+// before every minimum, and tiles with no qualifying element are skipped.
+// kPruned and kClosed:  A fixed dot i gets the penalty 2^100 added to
 // g_i, so every state that raises it scores above 2^99 and never wins, and
 // the tables are unchanged; row tiles that raise a fixed dot of 12..15 and
 // column tiles that raise a fixed dot of 4..7 are skipped.  A 0/1 operand
 // times the penalty is an exact 0 or the penalty, so the valid states score
 // exactly as in the dense form and the same error bound holds for them.
-template <int PREC, bool PRUNED>
+constexpr int kDense = 0, kPruned = 1, kClosed = 2;
+
+template <int PREC, int MODE>
 __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagRec *__restrict__ dr,
                                                     const PixRec *__restrict__ pr, int64_t P,
                                                     int32_t *__restrict__ n_out,
                                                     int64_t *__restrict__ counters)
 {
+    constexpr bool PRUNED = MODE != kDense;
+    constexpr bool CLOSED = MODE == kClosed;
     __shared__ float sT1[16][8];
     __shared__ float sT2[16][8];
     __shared__ float sH[256];
@@ -151,23 +162,31 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     const int li = lane & 15;
     float *gmrec = &sGm[threadIdx.x >> 6][0][0];
     double gnext = 0.0;
-    int nnext = 0;
+    int nnext = 0, knext = 0;
     uint32_t fnext = 0;
     if (wave < P) {
         gnext = pr[wave].g0[li];
         nnext = pr[wave].n0[li];
         if (PRUNED) fnext = pr[wave].free;
+        if (CLOSED) knext = pr[wave].k;
     }
+    // closed: popcount of this lane's element i within a tile (row bits
+    // 4q + i, column bits mrow)
+    int cq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cq[i] = __popc((uint32_t)(4 * q + i)) + __popc((uint32_t)mrow);
     for (int64_t pw = wave; pw < P; pw += nwaves) {
         const int64_t p = pw;
         const double gcur = gnext;
         const int ncur = nnext;
         // free dots of the pixel (a wave-uniform value)
         const uint32_t F = PRUNED ? __builtin_amdgcn_readfirstlane(fnext) : 0xFFFFu;
+        const int kc = CLOSED ? __builtin_amdgcn_readfirstlane(knext) : 0;
         if (pw + nwaves < P) {
             gnext = pr[pw + nwaves].g0[li];
             nnext = pr[pw + nwaves].n0[li];
             if (PRUNED) fnext = pr[pw + nwaves].free;
+            if (CLOSED) knext = pr[pw + nwaves].k;
         }
         // g0 beyond n is zero in the record; every lane gets all sixteen
         // (the error bound takes the unpenalised values)
@@ -180,11 +199,36 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(glp), i));
             gabs += fabsf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i)));
         }
-        if (PRUNED) ncand += 1ll << __popc(F & ((1u << n) - 1u));
+        if (MODE == kPruned) ncand += 1ll << __popc(F & ((1u << n) - 1u));
+        if (CLOSED) {
+            // C(free dots, k)
+            const int nf = __popc(F & ((1u << n) - 1u));
+            int64_t b = 1;
+            for (int j = 0; j < kc && j < nf; ++j) b = b * (nf - j) / (j + 1);
+            ncand += (kc >= 0 && kc <= nf) ? b : 0;
+        }
         // row tiles (high dots 12..15) and column tiles (low dots 4..7) that
-        // raise no fixed dot
-        auto rt_ok = [&](int rt) { return !PRUNED || !(((uint32_t)rt << 12) & ~F); };
+        // raise no fixed dot (closed: and that can hold k raised dots)
+        auto rt_ok = [&](int rt) {
+            if (!PRUNED) return true;
+            if (((uint32_t)rt << 12) & ~F) return false;
+            return !CLOSED || (kc - __popc((uint32_t)rt) >= 0 && kc - __popc((uint32_t)rt) <= 12);
+        };
         auto ct_ok = [&](int ct) { return !PRUNED || !(((uint32_t)ct << 4) & ~F); };
+        // closed: tile (rt, ct) holds a qualifying element, and the masking
+        auto tile_ok = [&](int rt, int ct) {
+            if (!CLOSED) return true;
+            const int r = kc - __popc((uint32_t)rt) - __popc((uint32_t)ct);
+            return r >= 0 && r <= 8;
+        };
+        auto qualify = [&](f32x4_t d, int rt, int ct) -> f32x4_t {
+            if (CLOSED) {
+                const int r = kc - __popc((uint32_t)rt) - __popc((uint32_t)ct);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d[i] = (cq[i] == r) ? d[i] : INFINITY;
+            }
+            return d;
+        };
         // per-lane row constants: G1 = g_lo + A_LH b_hi(row bits), P1 = b_hi(row)^T g_hi
         float G1[8];
 #pragma unroll
@@ -305,8 +349,8 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             if (PRUNED) {
 #pragma unroll
                 for (int ct = 0; ct < 16; ++ct) {
-                    if (!ct_ok(ct)) continue;
-                    const f32x4_t d = tile(a, af, ct);
+                    if (!ct_ok(ct) || !tile_ok(rt, ct)) continue;
+                    const f32x4_t d = qualify(tile(a, af, ct), rt, ct);
                     gm = fminf(fminf(gm, d[0]), d[1]);
                     gm2 = fminf(fminf(gm2, d[2]), d[3]);
                 }
@@ -351,8 +395,8 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             int ct1 = 0;
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct) {
-                if (!ct_ok(ct)) continue;
-                const f32x4_t d = tile(a, af, ct);
+                if (!ct_ok(ct) || !tile_ok(rtw, ct)) continue;
+                const f32x4_t d = qualify(tile(a, af, ct), rtw, ct);
                 const float tm = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
                 const bool lt = tm < t1;
                 t2 = lt ? t1 : fminf(t2, tm);
@@ -367,7 +411,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct)
-                if (ct == ctw) d = tile(a, af, ct);
+                if (ct == ctw) d = qualify(tile(a, af, ct), rtw, ct);
             float v1 = d[0], v2 = INFINITY;
             int i1 = 0;
 #pragma unroll
@@ -423,8 +467,8 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
             uint64_t inband = 0;  // bit 4 ct + i: element i of tile ct
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct) {
-                if (!ct_ok(ct)) continue;
-                const f32x4_t d = tile(a, af, ct);
+                if (!ct_ok(ct) || !tile_ok(rt, ct)) continue;
+                const f32x4_t d = qualify(tile(a, af, ct), rt, ct);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     if (d[i] <= thr) inband |= 1ull << (4 * ct + i);
@@ -470,7 +514,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
         block_add_counter(counters, C_NEAR_TIE, (int64_t)sflag);
         block_add_counter(counters, C_GAP_1E9, (int64_t)sgap);
         // dense: every pixel scores all 2^n candidates of its box
-        if (PRUNED) block_add_counter(counters, C_CANDIDATES, (int64_t)scand);
+        if (PRUNED) block_add_counter(counters, C_CANDIDATES, (int64_t)scand);  // summed per pixel
         else if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
     }
 }
@@ -480,9 +524,9 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
 template <typename Kernel>
 static int resident_blocks(Kernel kernel, int slot)
 {
-    static int cache[8][64];
+    static int cache[16][64];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || slot < 0 || slot >= 8) return 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || slot < 0 || slot >= 16) return 0;
     int &c = cache[slot][dev];
     if (c) return c;
     int cus = 0, per_cu = 0;
@@ -509,28 +553,25 @@ static hipError_t launch_persistent(Kernel kernel, int slot, const DiagRec *dr, 
     return hipGetLastError();
 }
 
-hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec,
-                             bool pruned, int32_t *n_out, int64_t *counters, int n_dot,
-                             hipStream_t s)
+hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec, int mode,
+                             int32_t *n_out, int64_t *counters, int n_dot, hipStream_t s)
 {
-    if (n_dot < 9 || n_dot > 16) return hipErrorInvalidValue;
+    if (n_dot < 9 || n_dot > 16 || mode < kDense || mode > kClosed) return hipErrorInvalidValue;
     if (P <= 0) return hipSuccess;
-    switch (prec * 2 + (pruned ? 1 : 0)) {
-    case kPrecFP32 * 2:
-        return launch_persistent(k_score_mfma<kPrecFP32, false>, 0, dr, pr, P, n_out, counters, s);
-    case kPrecX3 * 2:
-        return launch_persistent(k_score_mfma<kPrecX3, false>, 1, dr, pr, P, n_out, counters, s);
-    case kPrecX2 * 2:
-        return launch_persistent(k_score_mfma<kPrecX2, false>, 2, dr, pr, P, n_out, counters, s);
-    case kPrecFP32 * 2 + 1:
-        return launch_persistent(k_score_mfma<kPrecFP32, true>, 3, dr, pr, P, n_out, counters, s);
-    case kPrecX3 * 2 + 1:
-        return launch_persistent(k_score_mfma<kPrecX3, true>, 4, dr, pr, P, n_out, counters, s);
-    case kPrecX2 * 2 + 1:
-        return launch_persistent(k_score_mfma<kPrecX2, true>, 5, dr, pr, P, n_out, counters, s);
-    default:
-        return hipErrorInvalidValue;
-    }
+#define QA_SCORER_CASE(PR, MD, SLOT)                                                            \
+    if (prec == PR && mode == MD)                                                               \
+        return launch_persistent(k_score_mfma<PR, MD>, SLOT, dr, pr, P, n_out, counters, s);
+    QA_SCORER_CASE(kPrecFP32, kDense, 0)
+    QA_SCORER_CASE(kPrecX3, kDense, 1)
+    QA_SCORER_CASE(kPrecX2, kDense, 2)
+    QA_SCORER_CASE(kPrecFP32, kPruned, 3)
+    QA_SCORER_CASE(kPrecX3, kPruned, 4)
+    QA_SCORER_CASE(kPrecX2, kPruned, 5)
+    QA_SCORER_CASE(kPrecFP32, kClosed, 6)
+    QA_SCORER_CASE(kPrecX3, kClosed, 7)
+    QA_SCORER_CASE(kPrecX2, kClosed, 8)
+#undef QA_SCORER_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace qa

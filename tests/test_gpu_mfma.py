@@ -31,20 +31,23 @@ def say(*a):
     sys.stdout.flush()
 
 
-def compare(qa, oracle, d, prec, idx=None, t=1.0):
+def compare(qa, oracle, d, prec, idx=None, t=1.0, closed=False, nhat=0):
     V = torch.as_tensor(d.V).cuda()
-    n, st = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, t=t)
+    n, st = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, t=t, closed=closed,
+                            nhat=nhat)
     n = n.cpu().numpy()
     if idx is None:
         idx = np.arange(d.P)
-    ref = oracle.method_gs(d.cdd, d.cgd, d.V[idx], t=t)
+    ref = oracle.method_gs(d.cdd, d.cgd, d.V[idx], t=t, closed=closed, nhat=nhat)
     excl = (ref["e2"] - ref["e1"] < 1e-9) | ((ref["info"] & oracle.INFO_AMBIGUOUS) > 0)
     bad = (n[idx] != ref["n"]).any(1) & ~excl
     say("N=%d P=%d t=%.3f checked=%d prec=%s mismatches=%d excluded=%d near_tie=%d qp=%d "
         "candidates=%d" % (d.n_dot, d.P, t, len(idx), prec, bad.sum(), excl.sum(),
                            st["near_tie_pixels"], st["qp_pixels"], st["candidates"]))
     assert bad.sum() == 0, np.where(bad)[0][:10]
-    if t >= 1.0:
+    if closed:
+        assert (n[idx].sum(1) == nhat).all()
+    if t >= 1.0 and not closed:
         assert st["candidates"] == d.P << d.n_dot
     elif len(idx) == d.P:
         assert st["candidates"] == ref["ncand"].sum()
@@ -122,6 +125,26 @@ def test_thresholded_partial_high_index(qa, oracle, n_dot):
     for t in (0.8, 0.5, 0.25):
         compare(qa, oracle, d, "bf16x3", t=t)
     compare(qa, oracle, d, "fp32", t=0.5)
+
+
+@pytest.mark.parametrize("nhat", [8, 20, 30])
+@pytest.mark.parametrize("prec", PRECS)
+def test_grid16_closed(qa, oracle, prec, nhat):
+    """Closed 16-dot array (Sec. 2, constraint iii) on the matrix cores: the
+    subsets of the free dots with exactly k raised, every pixel against the
+    oracle, candidate counts C(free, k) summed."""
+    d = W.grid4x4(207, npix=12)
+    compare(qa, oracle, d, prec, closed=True, nhat=nhat)
+
+
+@pytest.mark.parametrize("n_dot", [9, 11, 12, 14])
+def test_closed_replica_and_thresholded(qa, oracle, n_dot):
+    """The paper's closed benchmark inputs (as many carriers as dots), dense
+    and thresholded (t < 1 closed pixels may double their threshold)."""
+    d = W.paper_replica(n_dot, seed=700 + n_dot, npix=15, closed=True)
+    for t in (1.0, 0.5, 0.2):
+        compare(qa, oracle, d, "bf16x3", t=t, closed=True, nhat=n_dot)
+    compare(qa, oracle, d, "fp32", closed=True, nhat=n_dot)
 
 
 def test_ragged_pixel_count(qa, oracle):
