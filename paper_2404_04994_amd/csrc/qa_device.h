@@ -335,13 +335,15 @@ __device__ __forceinline__ void prep_inverse(const double *sCdd, int n, double *
 #pragma unroll
                 for (int q = 0; q < 4; ++q) mk[q] = __shfl(m[q], (k << 2) | (tid & 3));
                 const double r = 1.0 / piv;
+                const double mr = -mik * r;  // the new column k
+                // branch-free selects (the four cases of the pivot map)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int j = j0 + q;
-                    if (i == k && j == k) m[q] = r;
-                    else if (i == k) m[q] = mk[q] * r;
-                    else if (j == k) m[q] = -mik * r;
-                    else m[q] = m[q] - mik * mk[q] * r;
+                    const double t1 = mk[q] * r;
+                    const double t2 = fma(-mik, t1, m[q]);
+                    const double v = (i == k) ? t1 : t2;
+                    m[q] = (j == k) ? ((i == k) ? r : mr) : v;
                 }
             }
         }
@@ -400,13 +402,15 @@ __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, dou
 #pragma unroll
             for (int q = 0; q < 4; ++q) mk[q] = __shfl(m[q], (k << 2) | (tid & 3));
             const double r = 1.0 / piv;
+            const double mr = -mik * r;  // the new column k
+            // branch-free selects (the four cases of the pivot map)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = j0 + q;
-                if (i == k && j == k) m[q] = r;
-                else if (i == k) m[q] = mk[q] * r;
-                else if (j == k) m[q] = -mik * r;
-                else m[q] = m[q] - mik * mk[q] * r;
+                const double t1 = mk[q] * r;
+                const double t2 = fma(-mik, t1, m[q]);
+                const double v = (i == k) ? t1 : t2;
+                m[q] = (j == k) ? ((i == k) ? r : mr) : v;
             }
         }
     }
