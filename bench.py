@@ -459,7 +459,12 @@ def run_extras(qa, W, torch, d, V, out, args):
         nb = max(3, steps // 10)
         wall = timed_calls(lambda: b.run(), nb, 1, torch)
         st = b.run(stats=True)
+        # HBM bytes the batch must move: the voltages in, n (int32) and <n>
+        # (FP64) out
+        hbm = sum(dg.P * (8 * dg.n_gate + 12 * dg.n_dot) for dg in b.diagrams)
         res["ragged_batch"] = {"diagrams": args.batch_diagrams, "pixels": b.pixels,
+                               "hbm_bytes": hbm,
+                               "hbm_GBps": round(hbm * nb / wall / 1e9, 1),
                                "ms_per_batch": round(1e3 * wall / nb, 3),
                                "pixels_per_s": round(b.pixels * nb / wall, 1),
                                "diagrams_per_s": round(args.batch_diagrams * nb / wall, 1),

@@ -302,6 +302,9 @@ qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, cons
         QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, scorer_mode(pb), n_out,
                                  w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
+    } else if (pb->n_dot <= 8) {
+        QA_HIP(launch_score_tab(w->dr, w->pr, P, n_out, w->counters, pb->n_dot, s));
+        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else {
         QA_HIP(launch_score_fp64(w->dr, w->pr, P, n_out, w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));

@@ -131,6 +131,9 @@ hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int
 // T = 0 argmin in FP64 over the candidate set of every pixel
 hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P, int32_t *n_out,
                              int64_t *counters, int n_dot, hipStream_t s);
+// the same in the table form (n_dot <= 8; the whole-box table from the setup)
+hipError_t launch_score_tab(const DiagRec *dr, const PixRec *pr, int64_t P, int32_t *n_out,
+                            int64_t *counters, int n_dot, hipStream_t s);
 // matrix-core scorer at T = 0; mode 0: the dense box, 1: the sub-box of each
 // pixel's free dots (thresholded), 2: closed arrays (subsets of the free
 // dots with k raised); near ties re-scored in FP64 inside the kernel

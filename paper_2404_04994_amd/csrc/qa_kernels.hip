@@ -674,6 +674,75 @@ __global__ __launch_bounds__(256) void k_soft_fwd_tab(const DiagRec *__restrict_
     }
 }
 
+// T = 0 argmin over the candidate set in the table form (n <= 8): the
+// candidate energies U(n0 + s) = U(n0) + g0 . s + h(s), h(s) = 1/2 s^T A s from
+// the whole-box table, CPL candidates per lane, groups of 2^LG lanes per
+// pixel; the same minimum, tie-break and runner-up as k_score_fp64.
+template <int LG, int NM, int CPL>
+__global__ __launch_bounds__(256) void k_score_tab(const DiagRec *__restrict__ dr,
+                                                   const PixRec *__restrict__ pr, int64_t P,
+                                                   int32_t *__restrict__ n_out,
+                                                   int64_t *__restrict__ counters)
+{
+    constexpr int G = 1 << LG;
+    __shared__ double sH[256];
+    __shared__ unsigned long long sc[2];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sH[i] = dr->hs[i];
+    if (threadIdx.x < 2) sc[threadIdx.x] = 0;
+    __syncthreads();
+    const int n = dr->n;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
+    const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
+    for (int64_t p = gid; p < P; p += ngroups) {
+        const PixRec *r = pr + p;
+        double g0[NM];
+#pragma unroll
+        for (int i = 0; i < NM; ++i) g0[i] = r->g0[i];
+        double e[CPL];
+        uint32_t st[CPL];
+        tab_energies<LG, NM, CPL>(sH, g0, r->u0, r->free, r->k, lane, e, st);
+        double e1 = INFINITY, e2 = INFINITY;
+        uint32_t s1 = 0;
+        int scored = 0;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            if (e[q] < INFINITY) ++scored;
+            if (better(e[q], st[q], e1, s1)) { e2 = e1; e1 = e[q]; s1 = st[q]; }
+            else if (e[q] < e2) e2 = e[q];
+        }
+#pragma unroll
+        for (int off = G / 2; off >= 1; off >>= 1) {
+            const double oe1 = __shfl_xor(e1, off, G);
+            const double oe2 = __shfl_xor(e2, off, G);
+            const uint32_t os1 = __shfl_xor(s1, off, G);
+            if (better(oe1, os1, e1, s1)) { e2 = fmin(e1, oe2); e1 = oe1; s1 = os1; }
+            else e2 = fmin(e2, oe1);
+        }
+        const int total = (int)group_sum<LG>((double)scored);
+        if (lane < n) n_out[p * n + lane] = (int32_t)r->n0[lane] + (int32_t)(s1 >> lane & 1u);
+        if (lane == 0) {
+            if (e2 - e1 < 1e-9) atomicAdd(&sc[0], 1ull);
+            atomicAdd(&sc[1], (unsigned long long)total);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        block_add_counter(counters, C_GAP_1E9, (int64_t)sc[0]);
+        block_add_counter(counters, C_CANDIDATES, (int64_t)sc[1]);
+    }
+}
+
+hipError_t launch_score_tab(const DiagRec *dr, const PixRec *pr, int64_t P, int32_t *n_out,
+                            int64_t *counters, int n_dot, hipStream_t s)
+{
+    if (n_dot < 1 || n_dot > 8) return hipErrorInvalidValue;
+    QA_DISPATCH_TAB(n_dot, hipLaunchKernelGGL((k_score_tab<LG_, NM_, CPL_>),
+                                              dim3(group_blocks(P, LG_, 8192)), dim3(256), 0, s,
+                                              dr, pr, P, n_out, counters));
+    return hipGetLastError();
+}
+
 hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
                            SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s)
 {
