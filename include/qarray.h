@@ -107,8 +107,19 @@ typedef struct {
     double kT;           /* >= 0; used by qa_soft_charge* only */
     double threshold;    /* t in [0,1]; 1 = the default 2^N box */
     int32_t precision;   /* qa_precision */
-    int32_t reserved;
+    int32_t flags;       /* QA_FLAG_* bits, 0 for the defaults */
 } qa_problem;
+
+/* qa_problem.flags.
+ *  QA_FLAG_EXHAUSTIVE : the matrix-core scorer computes the energy of every
+ *      state of the dense box.  By default the dense box of N >= 13 dots is
+ *      searched in bound order: a lower bound of the 256 states that share a
+ *      high part (the low part minimised over the reals, whose value is the
+ *      Schur complement of the low block of C_dd^{-1}, i.e. the inverse of the
+ *      high block of C_dd) discards high parts that cannot hold the argmin or
+ *      a state of the near-tie band.  Both give the argmin over the whole box
+ *      (Sec. 3.2.1); qa_stats.scored tells how many energies were computed. */
+#define QA_FLAG_EXHAUSTIVE 1
 
 typedef struct {
     int64_t pixels;            /* pixels processed */
@@ -117,7 +128,8 @@ typedef struct {
     int64_t doubled_pixels;    /* closed thresholded pixels whose t doubled */
     int64_t near_tie_pixels;   /* approximate scoring flagged -> FP64 re-score */
     int64_t fp64_gap_below_1e9;/* pixels whose FP64 best/runner-up gap < 1e-9 */
-    int64_t candidates;        /* candidate states scored (approximate pass) */
+    int64_t candidates;        /* states of the candidate sets (Sec. 3.2) */
+    int64_t scored;            /* states whose energy the scorer computed */
 } qa_stats;
 
 /* Ground state at T = 0 (Sec. 3, Eq. argmin) of P pixels.

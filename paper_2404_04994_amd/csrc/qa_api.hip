@@ -211,6 +211,8 @@ qa_status validate(const qa_problem *pb, bool need_kT)
         return fail(QA_E_RANGE, "the softargmin needs kT > 0 (got %g)", pb->kT);
     if (pb->precision < QA_PREC_FP64 || pb->precision > QA_PREC_BF16X2)
         return fail(QA_E_RANGE, "precision=%d unknown", pb->precision);
+    if (pb->flags & ~QA_FLAG_EXHAUSTIVE)
+        return fail(QA_E_RANGE, "flags=0x%x has unknown bits", (unsigned)pb->flags);
     return QA_OK;
 }
 
@@ -299,8 +301,9 @@ qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, cons
         QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else if (use_matrix_cores(pb)) {
-        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, scorer_mode(pb), n_out,
-                                 w->counters, pb->n_dot, s));
+        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, scorer_mode(pb),
+                                 (pb->flags & QA_FLAG_EXHAUSTIVE) != 0, n_out, w->counters,
+                                 pb->n_dot, s));
         if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     } else if (pb->n_dot <= 8) {
         QA_HIP(launch_score_tab(w->dr, w->pr, P, n_out, w->counters, pb->n_dot, s));
@@ -325,7 +328,7 @@ qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_
     std::array<hipEvent_t, 4> *ev = timing_slot(w);
     if (ev || !g_graphs) return enqueue_single(w, w->stream, pb, V, P, n_out, nbar, saved, ev);
     const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + 3 * pb->precision + scorer_mode(pb) : 1);
-    std::vector<int64_t> key = {pb->n_dot, pb->mode, path, P, (int64_t)(uintptr_t)V,
+    std::vector<int64_t> key = {pb->n_dot, pb->mode, path, pb->flags, P, (int64_t)(uintptr_t)V,
                                 (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
                                 (int64_t)(uintptr_t)saved, (int64_t)(uintptr_t)w->dr,
                                 (int64_t)(uintptr_t)w->pr,
@@ -382,6 +385,9 @@ qa_status read_stats(Workspace *w, qa_stats *stats)
     stats->near_tie_pixels = c[C_NEAR_TIE];
     stats->fp64_gap_below_1e9 = c[C_GAP_1E9];
     stats->candidates = c[C_CANDIDATES];
+    // only the bound-ordered search skips candidates; the other scorers
+    // compute every energy of the candidate set
+    stats->scored = c[C_SCORED] ? c[C_SCORED] : c[C_CANDIDATES];
     return QA_OK;
 }
 

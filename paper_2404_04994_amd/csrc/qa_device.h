@@ -382,8 +382,12 @@ __device__ __forceinline__ void prep_inverse(const double *sCdd, int n, double *
 // sum|A|/2 into red[5], by the same elimination as prep_inverse.  The other
 // waves of the block may be doing anything meanwhile; the caller's next
 // block barrier publishes M.
+//
+// The pivots run over the high dots 8..n-1 first, then 0..7: after the high
+// pivots the high block of the working matrix holds (C_dd,HH)^{-1}, which is
+// copied to S (8 x 8, identity past n - 8) when S is given.
 __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, double *M,
-                                                  double *red)
+                                                  double *red, double *S = nullptr)
 {
     const int tid = threadIdx.x;
     const int i = tid >> 2, j0 = 4 * (tid & 3);
@@ -394,7 +398,12 @@ __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, dou
         m[q] = (i < n && j < n) ? sCdd[i * kMaxDot + j] : (i == j ? 1.0 : 0.0);
     }
 #pragma unroll
-    for (int k = 0; k < kMaxDot; ++k) {
+    for (int kk = 0; kk < kMaxDot; ++kk) {
+        const int k = (kk + 8) & (kMaxDot - 1);
+        if (kk == 8 && S && i >= 8 && j0 >= 8) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) S[(i - 8) * 8 + j0 - 8 + q] = m[q];
+        }
         if (k < n) {
             const double mik = __shfl(m[k & 3], (i << 2) | (k >> 2));
             const double piv = __shfl(m[k & 3], (k << 2) | (k >> 2));
@@ -455,7 +464,8 @@ __device__ __forceinline__ void prep_store_core(DiagRec *dr, const double *M, co
 // The energy tables from A in LDS, spread over the waves of a grid: entry e
 // (of 256) goes to global wave e mod (number of waves), whose 64 lanes take
 // the 8 x 8 products b_x b_y A_xy and sum them.
-__device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M)
+__device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M,
+                                                   const double *S = nullptr)
 {
     const int n = dr->n;
     const int lane = threadIdx.x & (kWave - 1);
@@ -465,10 +475,14 @@ __device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M)
     const int nh = n - 8;
     for (int e = gw; e < 256; e += nw) {
         const bool both = (e >> x & 1) && (e >> y & 1);
-        double hl = 0.0, hh = 0.0;
+        double hl = 0.0, hh = 0.0, hs = 0.0, sa = 0.0;
         if (n >= 9) {
             hl = both ? M[x * kMaxDot + y] : 0.0;
             hh = (both && x < nh && y < nh) ? M[(8 + x) * kMaxDot + 8 + y] : 0.0;
+            if (S && x < nh && y < nh) {
+                hs = both ? S[x * 8 + y] : 0.0;
+                sa = fabs(S[x * 8 + y]);
+            }
         } else if (e < (1 << n)) {
             hl = both ? M[x * kMaxDot + y] : 0.0;
         }
@@ -476,8 +490,14 @@ __device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M)
         for (int off = 32; off >= 1; off >>= 1) {
             hl += __shfl_xor(hl, off, kWave);
             hh += __shfl_xor(hh, off, kWave);
+            hs += __shfl_xor(hs, off, kWave);
+            sa += __shfl_xor(sa, off, kWave);
         }
         if (lane == 0) {
+            if (n >= 9 && S) {
+                dr->Hs[e] = (e < (1 << nh)) ? (float)(0.5 * hs) : 1e30f;
+                if (e == 0) dr->sabsS = (float)(0.5 * sa);
+            }
             if (n >= 9) {
                 dr->hlo[e] = (float)(0.5 * hl);
                 dr->Hhi[e] = (e < (1 << nh)) ? (float)(0.5 * hh) : 1e30f;

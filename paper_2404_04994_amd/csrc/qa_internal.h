@@ -36,7 +36,7 @@ enum Counter {
     C_NEAR_TIE = 4,
     C_GAP_1E9 = 5,
     C_CANDIDATES = 6,
-    C_UNUSED7 = 7,
+    C_SCORED = 7,       // states whose approximate energy a scorer computed
     C_UNUSED8 = 8,
     C_UNUSED9 = 9,
     C_WORK = 10,        // work-queue shard cursor of the batched kernel
@@ -75,6 +75,12 @@ struct alignas(16) DiagRec {
     // FP64 copies of the matrix-core tables (the near-tie re-score)
     double T1d[16][8], T2d[16][8];
     double Hhid[256], hlod[256];
+    // bound-ordered search (N >= 9): with S = (C_dd,HH)^{-1}, the Schur
+    // complement of the low block in A, Hs = 1/2 b_hi^T S b_hi (1e30 past
+    // 2^(N-8))
+    float Hs[256];
+    float sabsS;                  // sum |S_ij| / 2
+    float pad2[3];
 };
 
 // bytes of a DiagRec the host uploads (the inputs)
@@ -88,6 +94,11 @@ struct alignas(8) PixRec {
     int32_t k;            // closed: number of raised free dots; -1 open
     int32_t flags;        // bit0 QP path, bit1 QP failure, bit2 threshold doubled
     int32_t pad;
+    // lower bound of the states of a high part b_hi (N >= 13, open):
+    // K + b_hi^T s + 1/2 b_hi^T S b_hi, s = S (n0 - x_u)_hi
+    float s[8];
+    float K;
+    int32_t pad1;
 };
 
 struct alignas(8) SavedRec {
@@ -136,9 +147,11 @@ hipError_t launch_score_tab(const DiagRec *dr, const PixRec *pr, int64_t P, int3
                             int64_t *counters, int n_dot, hipStream_t s);
 // matrix-core scorer at T = 0; mode 0: the dense box, 1: the sub-box of each
 // pixel's free dots (thresholded), 2: closed arrays (subsets of the free
-// dots with k raised); near ties re-scored in FP64 inside the kernel
+// dots with k raised); near ties re-scored in FP64 inside the kernel.  The
+// dense box of N >= 13 dots is searched in bound order unless exhaustive.
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec, int mode,
-                             int32_t *n_out, int64_t *counters, int n_dot, hipStream_t s);
+                             bool exhaustive, int32_t *n_out, int64_t *counters, int n_dot,
+                             hipStream_t s);
 hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
                            SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s);
 // adjoint partial sums into accA (kMaxDot^2), accG (kMaxDot x kMaxGate) and

@@ -162,6 +162,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     __shared__ double sA[kMaxDot * kMaxDot];    // A (symmetric), from wave 0
     __shared__ double sc[kMaxDot];              // C_dd 1
     __shared__ double red[8];                   // [4] 1^T C_dd 1, [5] sum|A| / 2
+    __shared__ double sS[64];                   // (C_dd,HH)^{-1}, from wave 0
     __shared__ double sG[kMaxGate * NM];        // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
     // the inputs into LDS in one pass; meanwhile 16 lanes of wave 0 form
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     if (!pixel_wave) {
         // the inverse is the block's critical path: its wave issues first
         __builtin_amdgcn_s_setprio(3);
-        prep_inverse_wave(sCdd, n, sA, red);
+        prep_inverse_wave(sCdd, n, sA, red, sS);
         __builtin_amdgcn_s_setprio(0);
     } else {
         // x_u = C_gd V
@@ -296,6 +297,16 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
 #pragma unroll
         for (int q = 0; q < NM; ++q) g0 += sA[q * kMaxDot + dot] * __shfl(z, base + q, kWave);
         const double u0 = 0.5 * group_dsum<NM>(z * g0);
+        // terms of the lower bound of the bound-ordered scorer (open, N >= 13):
+        // s = S z_hi and K = 1/2 z_hi^T s - U(n0)
+        double sv = 0.0, Kb = 0.0;
+        if (NM == 16 && !CLOSED && n >= 13) {
+            const int hd = dot >= 8 ? dot - 8 : 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sv += sS[hd * 8 + q] * __shfl(z, base + 8 + q, kWave);
+            sv = dot >= 8 ? sv : 0.0;
+            Kb = 0.5 * group_dsum<NM>(z * sv) - u0;
+        }
 
         if (p < P) {
             PixRec *o = pr + p;
@@ -303,7 +314,10 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
                 o->g0[q] = (q < NM) ? g0 : 0.0;
                 o->n0[q] = (int16_t)((q < NM) ? n0 : 0);
             }
+            if (dot >= 8) o->s[dot - 8] = (float)sv;
             if (dot == 0) {
+                o->K = (float)Kb;
+                o->pad1 = 0;
                 o->u0 = u0;
                 o->free = fm;
                 o->k = k;
@@ -330,7 +344,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         if (counters)
             for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0;
     }
-    prep_tables_spread(dr, sA);
+    prep_tables_spread(dr, sA, sS);
 }
 
 #define QA_DISPATCH_NM(n, CALL)                        \

@@ -59,6 +59,62 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi)
     return (fbits(lo) >> 16) | (fbits(hi) & 0xFFFF0000u);
 }
 
+// LDS writes of a wave made visible to all of its lanes (requests of one
+// wave are served in order; the fences keep the compiler from moving them)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cross-lane all-reductions without LDS: DPP within each 16-lane row
+// (exchange with lane ^ 1, lane ^ 2, then the mirror images within 8 and 16
+// lanes, each an involution, so after four steps every lane of a row holds
+// the row's result), then the row swaps of gfx950 for 16 and 32 lanes.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dppf(float x)
+{
+    return __uint_as_float(dpp32<CTRL>(__float_as_uint(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t r = (uint64_t)dpp32<CTRL>((uint32_t)u) |
+                       ((uint64_t)dpp32<CTRL>((uint32_t)(u >> 32)) << 32);
+    return __longlong_as_double((long long)r);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+__device__ __forceinline__ float row_min(float x)
+{
+    x = fminf(x, dppf<kDppXor1>(x));
+    x = fminf(x, dppf<kDppXor2>(x));
+    x = fminf(x, dppf<kDppHalfMirror>(x));
+    return fminf(x, dppf<kDppMirror>(x));
+}
+__device__ __forceinline__ double row_sum(double x)
+{
+    x += dppd<kDppXor1>(x);
+    x += dppd<kDppXor2>(x);
+    x += dppd<kDppHalfMirror>(x);
+    return x + dppd<kDppMirror>(x);
+}
+// minimum over the four rows of a value that is uniform within each row
+__device__ __forceinline__ float rows_min(float x)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = fminf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return fminf(__uint_as_float(t[0]), __uint_as_float(t[1]));
+}
+__device__ __forceinline__ float wave_min(float x) { return rows_min(row_min(x)); }
+
 constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
 
 #ifndef QA_SCORER_WAVES
@@ -519,6 +575,463 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
     }
 }
 
+// ---------------------------------------------------------------------------
+// Bound-ordered search of the dense box (N >= 13: more than one row tile).
+//
+// The argmin over the 2^N states of the box is found without scoring all of
+// them.  With y = n0 - x_u (so g = A y and U(n0 + b) - U(n0) = b^T g +
+// 1/2 b^T A b = 1/2 (y + b)^T A (y + b) - 1/2 y^T A y), fixing the high part
+// b_hi and minimising over a real-valued low part b_lo gives the Schur
+// complement of A_LL in A, which is (C_dd,HH)^{-1} =: S:
+//     E(b_hi, b_lo) >= L(b_hi) = K + b_hi^T s + 1/2 b_hi^T S b_hi,
+//     s = S y_hi,  K = 1/2 y_hi^T s - U(n0)
+// (the setup forms S in its Gauss-Jordan sweep, the table of
+// 1/2 b_hi^T S b_hi, and s and K of every pixel in FP64).
+// L is a lower bound for all 256 states of a high index, so a high index
+// whose bound lies above the best energy found so far (plus a margin that
+// covers the FP32 error of the bound and three times the certified error
+// band) holds neither the exact argmin nor any state of the near-tie band.
+// Each pixel scores the row tile with the smallest bound first, then only
+// the other high indices whose bound does not exceed the best energy so far
+// plus the margin, sixteen to a tile (a row of the tile is any high index);
+// the rest of the kernel (error band, FP64 re-score of near ties) is that of
+// the dense scorer over the scored rows.  The result is the argmin over the
+// whole box, as in the dense form.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const DiagRec *__restrict__ dr,
+                                                     const PixRec *__restrict__ pr, int64_t P,
+                                                     int32_t *__restrict__ n_out,
+                                                     int64_t *__restrict__ counters)
+{
+    __shared__ float sT1[16][8];
+    __shared__ float sT2[16][8];
+    __shared__ float sH[256];
+    __shared__ float sHs[256];                   // 1/2 b_hi^T S b_hi (1e30 beyond 2^(N-8))
+    __shared__ double sT1d[16][8], sT2d[16][8];  // FP64 tables of the near-tie re-score
+    __shared__ double sHd[256], sLd[256];
+    __shared__ double sG64[4][kMaxDot];
+    __shared__ uint2 sCt[4][256];                // per wave: C(c_hi) of its pixel (BF16 parts / FP32)
+    __shared__ uint8_t sList[4][256];            // per wave: high index of every scored row
+    __shared__ unsigned long long sflag, sgap, srows;
+    const int n = dr->n;
+    const int nh = n - 8;
+    const int nrt = 1 << (nh - 4);
+    for (int e = threadIdx.x; e < 128; e += blockDim.x) {
+        sT1[e / 8][e % 8] = dr->T1[e / 8][e % 8];
+        sT2[e / 8][e % 8] = dr->T2[e / 8][e % 8];
+        sT1d[e / 8][e % 8] = dr->T1d[e / 8][e % 8];
+        sT2d[e / 8][e % 8] = dr->T2d[e / 8][e % 8];
+    }
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        sH[e] = dr->Hhi[e];
+        sHd[e] = dr->Hhid[e];
+        sLd[e] = dr->hlod[e];
+        sHs[e] = dr->Hs[e];
+    }
+    if (threadIdx.x == 0) { sflag = 0; sgap = 0; srows = 0; }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int q = lane >> 4;
+    const int mrow = lane & 15;
+    const int li = lane & 15;
+    const float sumabs = dr->sumabs;
+    const float hsabs = dr->sabsS;
+
+    // pixel-independent column operands (as in the dense scorer)
+    uint32_t bw[16][4];
+    float bf[16][3];
+#pragma unroll
+    for (int ct = 0; ct < 16; ++ct) {
+        const int clo = ct * 16 + mrow;
+        const float h = dr->hlo[clo];
+        if (PREC == kPrecFP32) {
+            bf[ct][0] = (float)((clo >> q) & 1);
+            bf[ct][1] = (float)((clo >> (4 + q)) & 1);
+            bf[ct][2] = (q == 0) ? 1.0f : (q == 1 ? h : 0.0f);
+        } else {
+            if (q < 3) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    bw[ct][d] = ((clo >> (2 * d) & 1) ? 0x3F80u : 0u) |
+                                ((clo >> (2 * d + 1) & 1) ? 0x3F800000u : 0u);
+            } else {
+                const float h1 = trunc16(h);
+                const float r = h - h1;
+                const float h2 = trunc16(r);
+                const float h3 = r - h2;
+                bw[ct][0] = 0x3F803F80u;
+                bw[ct][1] = 0x3F80u | (fbits(h1) & 0xFFFF0000u);
+                bw[ct][2] = pack2(h2, h3);
+                bw[ct][3] = 0u;
+            }
+        }
+    }
+    // constant chunk of an unused row: C = 1e30, so its states never win
+    uint2 csent;
+    {
+        const float C = 1e30f;
+        const float c1 = trunc16(C);
+        const float cr = C - c1;
+        const float c2 = trunc16(cr);
+        csent = (PREC == kPrecFP32) ? make_uint2(fbits(C), 0u)
+                                    : make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
+    }
+
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t nflag = 0, ngap = 0, nrows = 0;
+    uint2 *ctab = sCt[wv];
+    uint8_t *list = sList[wv];
+    double *g64 = sG64[wv];
+    // lane i < 16 holds g0_i and n0_i, lanes 8..15 also s_{i-8}, lane 0 K
+    // (vector loads, one pixel ahead)
+    double gnext = 0.0;
+    int nnext = 0;
+    float snext = 0.0f;
+    if (wave < P) {
+        gnext = pr[wave].g0[li];
+        nnext = pr[wave].n0[li];
+        snext = (li >= 8) ? pr[wave].s[li - 8] : pr[wave].K;
+    }
+    for (int64_t p = wave; p < P; p += nwaves) {
+        const double gcur = gnext;
+        const int ncur = nnext;
+        const float scur = snext;
+        if (p + nwaves < P) {
+            gnext = pr[p + nwaves].g0[li];
+            nnext = pr[p + nwaves].n0[li];
+            snext = (li >= 8) ? pr[p + nwaves].s[li - 8] : pr[p + nwaves].K;
+        }
+        const float gl = (float)gcur;
+        float g[16];
+        float gabs = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i));
+            gabs += fabsf(g[i]);
+        }
+        // ---- the bound terms of the setup: s = S (n0 - x_u)_hi and K ----
+        if (lane < kMaxDot) g64[lane] = gcur;  // FP64 g of the near-tie re-score
+        float sb[8];
+        float sabs = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            sb[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scur), 8 + i));
+            sabs += fabsf(sb[i]);
+        }
+        const float Kf = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scur), 0));
+        // Certified bound on |E_approx - E| (as in the dense scorer), and the
+        // FP32 error of the bound: at most a dozen roundings of partial sums
+        // that are bounded by |K| + sum|s| + 1/2 sum|S|; 2^-19 of that covers
+        // them with room to spare.
+        const float S = gabs + sumabs;
+        const float delta = (PREC == kPrecX2 ? 0x1p-15f : 0x1p-17f) * S;
+        const float margin = 4.0f * delta + 0x1p-19f * (fabsf(Kf) + sabs + hsabs);
+
+        // ---- per lane: bound and constant chunk of high indices (q + 4 e) * 16 + row ----
+        float P1 = 0.0f, R1 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (mrow >> j & 1) {
+                P1 += g[8 + j];
+                R1 += sb[j];
+            }
+        }
+        float lb[4];
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4) {
+            const int rt = q + 4 * e4;
+            float P2 = 0.0f, R2 = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (rt >> j & 1) {
+                    P2 += g[12 + j];
+                    R2 += sb[4 + j];
+                }
+            }
+            const int chi = rt * 16 + mrow;
+            lb[e4] = (rt < nrt) ? ((Kf + R1) + R2) + sHs[chi] : INFINITY;
+            const float C = (P1 + P2) + sH[chi];
+            if (PREC == kPrecFP32) {
+                ctab[chi] = make_uint2(fbits(C), 0u);
+            } else {
+                const float c1 = trunc16(C);
+                const float cr = C - c1;
+                const float c2 = trunc16(cr);
+                ctab[chi] = make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
+            }
+        }
+        // row tile with the smallest bound
+        float rlb[4];
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4) rlb[e4] = row_min(lb[e4]);
+        float mb = rlb[0];
+        int me = 0;
+#pragma unroll
+        for (int e4 = 1; e4 < 4; ++e4)
+            if (rlb[e4] < mb) { mb = rlb[e4]; me = e4; }
+        const float gmb = rows_min(mb);
+        const unsigned long long hb = __ballot(mb == gmb);
+        const int wl = __ffsll((long long)hb) - 1;
+        const int rts = __builtin_amdgcn_readlane(q + 4 * me, wl);
+        if (lane < 16) list[lane] = (uint8_t)(rts * 16 + lane);
+        wave_sync();  // the constant chunks and the first tile's rows
+
+        // g_{2q}, g_{2q+1} (split-BF16 forms) or g_q, g_{4+q} (FP32) of this lane
+        float ga = g[0], gb = g[1];
+#pragma unroll
+        for (int d = 1; d < 4; ++d) {
+            if (q == d) {
+                ga = (PREC == kPrecFP32) ? g[d] : g[2 * d];
+                gb = (PREC == kPrecFP32) ? g[4 + d] : g[2 * d + 1];
+            }
+        }
+        if (PREC == kPrecFP32) gb = (q == 0) ? g[4] : gb;
+        int cnt = 16;  // scored rows so far (wave-uniform)
+
+        // A operand of tile t: row r of the tile is high index list[16 t + r]
+        // (unused rows past cnt get the sentinel constant chunk)
+        auto build_rows = [&](int t, Pack8 &a, float (&af)[3]) {
+            const int idx = t * 16 + mrow;
+            const bool real = idx < cnt;
+            const int chi = real ? (int)list[idx] : 0;
+            const int row = chi & 15, rtt = chi >> 4;
+            const uint2 cw = real ? ctab[chi] : csent;
+            if (PREC == kPrecFP32) {
+                const float v0 = (ga + sT1[row][q]) + sT2[rtt][q];
+                const float v1 = (gb + sT1[row][4 + q]) + sT2[rtt][4 + q];
+                af[0] = v0;
+                af[1] = v1;
+                af[2] = (q == 0) ? __uint_as_float(cw.x) : (q == 1 ? 1.0f : 0.0f);
+            } else {
+                const float v0 = (ga + sT1[row][2 * q]) + sT2[rtt][2 * q];
+                const float v1 = (gb + sT1[row][2 * q + 1]) + sT2[rtt][2 * q + 1];
+                uint32_t R0, R1, R2;
+                if (PREC == kPrecX3) {
+                    const float a0 = trunc16(v0), b0 = trunc16(v1);
+                    const float r0 = v0 - a0, s0 = v1 - b0;
+                    const float a1 = trunc16(r0), b1 = trunc16(s0);
+                    R0 = pack2(a0, b0);
+                    R1 = pack2(a1, b1);
+                    R2 = pack2(r0 - a1, s0 - b1);
+                } else {
+                    const float a0 = rne16(v0), b0 = rne16(v1);
+                    R0 = pack2(a0, b0);
+                    R1 = pack2(rne16(v0 - a0), rne16(v1 - b0));
+                    R2 = 0u;
+                }
+                uint32_t R3 = (q == 2) ? 0x3F803F80u : 0u;
+                R3 = (q == 1) ? cw.y : R3;
+                R3 = (q == 0) ? cw.x : R3;
+                const auto t02 = __builtin_amdgcn_permlane32_swap(R0, R2, false, false);
+                const auto t13 = __builtin_amdgcn_permlane32_swap(R1, R3, false, false);
+                const auto u01 = __builtin_amdgcn_permlane16_swap(t02[0], t13[0], false, false);
+                const auto u23 = __builtin_amdgcn_permlane16_swap(t02[1], t13[1], false, false);
+                a.u[0] = u01[0];
+                a.u[1] = u01[1];
+                a.u[2] = u23[0];
+                a.u[3] = u23[1];
+            }
+        };
+        auto tile = [&](const Pack8 &a, const float (&af)[3], int ct) -> f32x4_t {
+            f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (PREC == kPrecFP32) {
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[ct][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[ct][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[ct][2], acc, 0, 0, 0);
+            } else {
+                Pack8 b;
+                b.u[0] = bw[ct][0]; b.u[1] = bw[ct][1]; b.u[2] = bw[ct][2]; b.u[3] = bw[ct][3];
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+            }
+            return acc;
+        };
+        // per lane: smallest group minimum b1 (tile * 16 + ct in a1) and the
+        // second smallest group minimum b2
+        float b1 = INFINITY, b2 = INFINITY;
+        int a1 = 0;
+        auto track = [&](const f32x4_t &d, int code) {
+            const float m = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
+            const bool lt = m < b1;
+            b2 = fminf(b2, fmaxf(b1, m));
+            b1 = fminf(b1, m);
+            a1 = lt ? code : a1;
+        };
+        // software-pipelined: tile ct - 1 is tracked while tile ct is on the
+        // matrix core
+        auto score_tile = [&](int t) {
+            Pack8 a;
+            float af[3];
+            build_rows(t, a, af);
+            f32x4_t dp = tile(a, af, 0);
+#pragma unroll
+            for (int ct = 1; ct < 16; ++ct) {
+                const f32x4_t d = tile(a, af, ct);
+                track(dp, t * 16 + ct - 1);
+                dp = d;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            track(dp, t * 16 + 15);
+        };
+        score_tile(0);
+        // the other high indices whose bound admits a state within the margin
+        // of the best so far, compacted into the list
+        {
+            const float thr = wave_min(b1) + margin;
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int rt = q + 4 * e4;
+                const bool take = lb[e4] <= thr && rt != rts;
+                const unsigned long long m = __ballot(take);
+                if (take)
+                    list[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0))] =
+                        (uint8_t)(rt * 16 + mrow);
+                cnt += __popcll(m);
+            }
+            wave_sync();
+        }
+        const int ntiles = (cnt + 15) >> 4;
+        for (int t = 1; t < ntiles; ++t) score_tile(t);
+        nrows += cnt;
+
+        // ---- best over the wave, runner-up bound, winner's tile once more ----
+        const float wmin = wave_min(b1);
+        const unsigned long long hit = __ballot(b1 == wmin);
+        const int winner = __ffsll((long long)hit) - 1;
+        const float other = wave_min((lane == winner) ? b2 : b1);
+        const int aw = __builtin_amdgcn_readlane(a1, winner);
+        const int tw = aw >> 4, ctw = aw & 15;
+        float e1, e2;
+        int iw;
+        {
+            Pack8 a;
+            float af[3];
+            build_rows(tw, a, af);
+            f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ct = 0; ct < 16; ++ct)
+                if (ct == ctw) d = tile(a, af, ct);
+            float v1 = d[0], v2 = INFINITY;
+            int i1 = 0;
+#pragma unroll
+            for (int i = 1; i < 4; ++i) {
+                if (d[i] < v1) { v2 = v1; v1 = d[i]; i1 = i; }
+                else v2 = fminf(v2, d[i]);
+            }
+            e1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v1), winner));
+            iw = __builtin_amdgcn_readlane(i1, winner);
+            e2 = fminf(other, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v2), winner)));
+        }
+        const bool tie = !(e2 - e1 > 2.0f * delta);
+        if (!tie) {
+            if (lane < n) {
+                const int row = 4 * (winner >> 4) + iw;
+                const uint32_t chi = list[tw * 16 + row];
+                const uint32_t clo = (uint32_t)(ctw * 16 + (winner & 15));
+                const uint32_t b = clo | (chi << 8);
+                n_out[p * n + lane] = ncur + (int32_t)((b >> lane) & 1u);
+            }
+            continue;
+        }
+        // ---- near tie: the scored rows once more, each lane scores its own
+        // in-band states in FP64 (ties to the lexicographically smallest) ----
+        ++nflag;
+        const float thr = e1 + 2.0f * delta;
+        double c1best = INFINITY, c2best = INFINITY;
+        uint32_t cbest = 0;
+        for (int t = 0; t < ntiles; ++t) {
+            Pack8 a;
+            float af[3];
+            build_rows(t, a, af);
+            uint32_t ib[2] = {0u, 0u};  // bit 4 ct + i: element i of tile ct
+#pragma unroll
+            for (int ct = 0; ct < 16; ++ct) {
+                const f32x4_t d = tile(a, af, ct);
+                const float dm = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
+                if (dm <= thr) {
+                    uint32_t m4 = 0u;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) m4 |= (d[i] <= thr) ? 1u << i : 0u;
+                    ib[ct >> 3] |= m4 << (4 * (ct & 7));
+                }
+            }
+            uint64_t inband = ((uint64_t)ib[1] << 32) | ib[0];
+            while (inband) {
+                // keep the FP64 tables in LDS (loads not hoisted into registers)
+                __asm__ volatile("" ::: "memory");
+                const int bit = __ffsll((long long)inband) - 1;
+                inband &= inband - 1;
+                const uint32_t clo = (uint32_t)((bit >> 2) * 16 + mrow);
+                const uint32_t chi = list[t * 16 + 4 * q + (bit & 3)];
+                const uint32_t c = clo | (chi << 8);
+                const int row = chi & 15, rth = chi >> 4;
+                double e = sLd[clo] + sHd[chi];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (chi >> i & 1u) e += g64[8 + i];
+                    if (clo >> i & 1u) e += (g64[i] + sT1d[row][i]) + sT2d[rth][i];
+                }
+                if (e < c1best || (e == c1best && __brev(c) < __brev(cbest))) {
+                    c2best = c1best; c1best = e; cbest = c;
+                } else {
+                    c2best = fmin(c2best, e);
+                }
+            }
+        }
+        // (best, runner-up, state) over the wave: exchange with the partner
+        // lanes of the row steps, then combine the swapped rows
+        auto merge = [&](double ob1, double ob2, uint32_t oc1) {
+            if (ob1 < c1best || (ob1 == c1best && __brev(oc1) < __brev(cbest))) {
+                c2best = fmin(c1best, ob2); c1best = ob1; cbest = oc1;
+            } else {
+                c2best = fmin(c2best, ob1);
+            }
+        };
+        merge(dppd<kDppXor1>(c1best), dppd<kDppXor1>(c2best), dpp32<kDppXor1>(cbest));
+        merge(dppd<kDppXor2>(c1best), dppd<kDppXor2>(c2best), dpp32<kDppXor2>(cbest));
+        merge(dppd<kDppHalfMirror>(c1best), dppd<kDppHalfMirror>(c2best),
+              dpp32<kDppHalfMirror>(cbest));
+        merge(dppd<kDppMirror>(c1best), dppd<kDppMirror>(c2best), dpp32<kDppMirror>(cbest));
+        {
+            // rows 2k and 2k + 1, then the two halves: the swaps hand each lane
+            // its own value and the partner's, in an order that depends on the
+            // lane, so both are merged into a fresh triple
+            auto swap_merge = [&](auto swap) {
+                const uint64_t u1 = (uint64_t)__double_as_longlong(c1best);
+                const uint64_t u2 = (uint64_t)__double_as_longlong(c2best);
+                const auto l1 = swap((uint32_t)u1), h1 = swap((uint32_t)(u1 >> 32));
+                const auto l2 = swap((uint32_t)u2), h2 = swap((uint32_t)(u2 >> 32));
+                const auto cc = swap(cbest);
+                const double x1 = __longlong_as_double((long long)((uint64_t)l1[0] | ((uint64_t)h1[0] << 32)));
+                const double y1 = __longlong_as_double((long long)((uint64_t)l1[1] | ((uint64_t)h1[1] << 32)));
+                const double x2 = __longlong_as_double((long long)((uint64_t)l2[0] | ((uint64_t)h2[0] << 32)));
+                const double y2 = __longlong_as_double((long long)((uint64_t)l2[1] | ((uint64_t)h2[1] << 32)));
+                c1best = x1; c2best = x2; cbest = cc[0];
+                merge(y1, y2, cc[1]);
+            };
+            swap_merge([](uint32_t v) { return __builtin_amdgcn_permlane16_swap(v, v, false, false); });
+            swap_merge([](uint32_t v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false); });
+        }
+        if (lane < n) n_out[p * n + lane] = ncur + (int32_t)((cbest >> lane) & 1u);
+        if (lane == 0 && c2best - c1best < 1e-9) ++ngap;
+    }
+    if (lane == 0) {
+        if (nflag) atomicAdd(&sflag, (unsigned long long)nflag);
+        if (ngap) atomicAdd(&sgap, (unsigned long long)ngap);
+        if (nrows) atomicAdd(&srows, (unsigned long long)nrows);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        block_add_counter(counters, C_NEAR_TIE, (int64_t)sflag);
+        block_add_counter(counters, C_GAP_1E9, (int64_t)sgap);
+        block_add_counter(counters, C_SCORED, (int64_t)srows << 8);  // 256 states per row
+        if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
+    }
+}
+
 // blocks of 256 threads of a scorer kernel that fit on the device at once
 // (cached per kernel slot and device; 0 if unknown)
 template <typename Kernel>
@@ -554,10 +1067,20 @@ static hipError_t launch_persistent(Kernel kernel, int slot, const DiagRec *dr, 
 }
 
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec, int mode,
-                             int32_t *n_out, int64_t *counters, int n_dot, hipStream_t s)
+                             bool exhaustive, int32_t *n_out, int64_t *counters, int n_dot,
+                             hipStream_t s)
 {
     if (n_dot < 9 || n_dot > 16 || mode < kDense || mode > kClosed) return hipErrorInvalidValue;
     if (P <= 0) return hipSuccess;
+    if (mode == kDense && n_dot >= 13 && !exhaustive) {
+        if (prec == kPrecFP32)
+            return launch_persistent(k_score_bound<kPrecFP32>, 9, dr, pr, P, n_out, counters, s);
+        if (prec == kPrecX3)
+            return launch_persistent(k_score_bound<kPrecX3>, 10, dr, pr, P, n_out, counters, s);
+        if (prec == kPrecX2)
+            return launch_persistent(k_score_bound<kPrecX2>, 11, dr, pr, P, n_out, counters, s);
+        return hipErrorInvalidValue;
+    }
 #define QA_SCORER_CASE(PR, MD, SLOT)                                                            \
     if (prec == PR && mode == MD)                                                               \
         return launch_persistent(k_score_mfma<PR, MD>, SLOT, dr, pr, P, n_out, counters, s);

@@ -36,13 +36,16 @@ class Problem(C.Structure):
                 ("cdd", C.POINTER(C.c_double)), ("cgd", C.POINTER(C.c_double)),
                 ("mode", C.c_int32), ("n_charge", C.c_int32),
                 ("kT", C.c_double), ("threshold", C.c_double),
-                ("precision", C.c_int32), ("reserved", C.c_int32)]
+                ("precision", C.c_int32), ("flags", C.c_int32)]
+
+
+FLAG_EXHAUSTIVE = 1
 
 
 class Stats(C.Structure):
     _fields_ = [(name, C.c_int64) for name in
                 ("pixels", "qp_pixels", "qp_failures", "doubled_pixels", "near_tie_pixels",
-                 "fp64_gap_below_1e9", "candidates")]
+                 "fp64_gap_below_1e9", "candidates", "scored")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -107,7 +110,7 @@ def _host(m):
     return np.ascontiguousarray(m, dtype=np.float64)
 
 
-def make_problem(cdd, cgd, closed=False, nhat=0, kT=0.0, t=1.0, precision="fp64"):
+def make_problem(cdd, cgd, closed=False, nhat=0, kT=0.0, t=1.0, precision="fp64", flags=0):
     """Problem struct plus the host arrays it points into (keep both alive)."""
     cdd, cgd = _host(cdd), _host(cgd)
     if cdd.ndim != 2 or cgd.ndim != 2 or cdd.shape[0] != cdd.shape[1] or cgd.shape[0] != cdd.shape[0]:
@@ -115,7 +118,7 @@ def make_problem(cdd, cgd, closed=False, nhat=0, kT=0.0, t=1.0, precision="fp64"
     prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
     pb = Problem(cdd.shape[0], cgd.shape[1], cdd.ctypes.data_as(C.POINTER(C.c_double)),
                  cgd.ctypes.data_as(C.POINTER(C.c_double)), QA_CLOSED if closed else QA_OPEN,
-                 int(nhat), float(kT), float(t), prec, 0)
+                 int(nhat), float(kT), float(t), prec, int(flags))
     return pb, (cdd, cgd)
 
 
@@ -129,11 +132,14 @@ def _device_V(V, n_gate):
 
 
 def ground_state(cdd, cgd, V, closed=False, nhat=0, t=1.0, precision="fp64", stream=None,
-                 stats=False, out=None):
+                 stats=False, out=None, exhaustive=False):
     """T = 0 ground state of every pixel (Eq. argmin); int32 tensor (P, N) on the GPU.
-    With stats=True returns (n, stats_dict) and waits for the stream."""
+    With stats=True returns (n, stats_dict) and waits for the stream.
+    exhaustive=True makes the matrix-core scorer compute every energy of the
+    dense box instead of searching it in bound order (same result)."""
     lib = load()
-    pb, keep = make_problem(cdd, cgd, closed, nhat, 0.0, t, precision)
+    pb, keep = make_problem(cdd, cgd, closed, nhat, 0.0, t, precision,
+                            FLAG_EXHAUSTIVE if exhaustive else 0)
     V = _device_V(V, pb.n_gate)
     P = V.shape[0]
     if out is None:

@@ -62,6 +62,7 @@ GOOD_CGD = np.array([[0.8, 0.1], [0.1, 0.9]])
     (GOOD_CDD, GOOD_CGD, dict(t=-0.1), 5),                             # t < 0
     (GOOD_CDD, GOOD_CGD, dict(closed=True, nhat=-1), 5),               # N_hat < 0
     (GOOD_CDD, GOOD_CGD, dict(precision=7), 5),                        # bad enum
+    (GOOD_CDD, GOOD_CGD, dict(flags=2), 5),                            # unknown flag bit
 ])
 def test_validation_errors(qa, cdd, cgd, kw, status):
     st, msg = _call_gs(qa, cdd, cgd, **kw)

@@ -181,3 +181,37 @@ def test_graph_replays_match_eager(qa, oracle):
             assert torch.equal(nb.cpu(), ref_soft), i
     finally:
         qa.graphs_enable(False)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_bound_order_equals_exhaustive(qa, prec):
+    """The bound-ordered search of the dense box (N >= 13) returns, at every
+    pixel of the full 100 x 100 16-dot diagram, the state the exhaustive
+    scorer returns, while computing a fraction of the energies."""
+    d = W.grid4x4(200)
+    V = torch.as_tensor(d.V).cuda()
+    nb, sb = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True)
+    ne, se = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, exhaustive=True)
+    diff = (nb.cpu().numpy() != ne.cpu().numpy()).any(1).sum()
+    say("%s: bound scored %d of %d states (%.2f%%), near ties %d / exhaustive %d, diff %d"
+        % (prec, sb["scored"], sb["candidates"], 100.0 * sb["scored"] / sb["candidates"],
+           sb["near_tie_pixels"], se["near_tie_pixels"], diff))
+    assert diff == 0
+    assert sb["candidates"] == se["candidates"] == d.P << 16
+    assert se["scored"] == se["candidates"]
+    assert 16 * 256 * d.P <= sb["scored"] < sb["candidates"] // 2
+
+
+@pytest.mark.parametrize("n_dot,seed", [(13, 601), (14, 602), (15, 603), (16, 604)])
+def test_bound_order_paper_replica(qa, oracle, n_dot, seed):
+    """Random capacitances of the paper's benchmark (Sec. 7), 13..16 dots:
+    the bound-ordered search against the oracle at every pixel, and against
+    the exhaustive scorer."""
+    d = W.paper_replica(n_dot, seed=seed, npix=24)
+    n, st = compare(qa, oracle, d, "bf16x3")
+    V = torch.as_tensor(d.V).cuda()
+    ne = qa.ground_state(d.cdd, d.cgd, V, precision="bf16x3", exhaustive=True).cpu().numpy()
+    assert (n == ne).all()
+    assert st["scored"] < st["candidates"]
+    compare(qa, oracle, d, "fp32")
+    compare(qa, oracle, d, "bf16x2")
