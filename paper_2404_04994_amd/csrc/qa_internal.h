@@ -52,6 +52,55 @@ __device__ __forceinline__ void block_add_counter(int64_t *counters, int which, 
                   (unsigned long long)v);
 }
 
+// Cross-lane all-reductions without LDS: DPP within each 16-lane row
+// (exchange with lane ^ 1, lane ^ 2, then the mirror images within 8 and 16
+// lanes, each an involution, so after four steps every lane of a row holds
+// the row's result), then the row swaps of gfx950 for 16 and 32 lanes.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dppf(float x)
+{
+    return __uint_as_float(dpp32<CTRL>(__float_as_uint(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t r = (uint64_t)dpp32<CTRL>((uint32_t)u) |
+                       ((uint64_t)dpp32<CTRL>((uint32_t)(u >> 32)) << 32);
+    return __longlong_as_double((long long)r);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+// lane i of every 16-lane row to the whole row
+constexpr int kDppRowBcast0 = 0x150;
+__device__ __forceinline__ float row_min(float x)
+{
+    x = fminf(x, dppf<kDppXor1>(x));
+    x = fminf(x, dppf<kDppXor2>(x));
+    x = fminf(x, dppf<kDppHalfMirror>(x));
+    return fminf(x, dppf<kDppMirror>(x));
+}
+__device__ __forceinline__ double row_sum(double x)
+{
+    x += dppd<kDppXor1>(x);
+    x += dppd<kDppXor2>(x);
+    x += dppd<kDppHalfMirror>(x);
+    return x + dppd<kDppMirror>(x);
+}
+// minimum over the four rows of a value that is uniform within each row
+__device__ __forceinline__ float rows_min(float x)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = fminf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return fminf(__uint_as_float(t[0]), __uint_as_float(t[1]));
+}
+__device__ __forceinline__ float wave_min(float x) { return rows_min(row_min(x)); }
+
 struct alignas(16) DiagRec {
     // inputs (written by the host, or by k_prep_batch): everything up to Cgd
     int32_t n, g, closed, nhat;

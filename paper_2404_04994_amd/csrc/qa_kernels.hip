@@ -15,6 +15,8 @@
 //   k_soft_bwd  its adjoint with respect to C_dd, C_gd and V.
 #include "qa_device.h"
 
+#include <type_traits>
+
 namespace qa {
 
 __global__ void k_zero_i64(int64_t *p, int n)
@@ -88,28 +90,67 @@ __device__ __forceinline__ uint32_t group_ballot(bool pred)
     return (uint32_t)((b >> sh) & ((1ull << NM) - 1ull));
 }
 
+// Group reductions: a group of 16 is a DPP row (row-local exchanges, no
+// LDS); smaller groups use shuffles.
 template <int NM>
 __device__ __forceinline__ int group_isum(int v)
 {
+    if constexpr (NM == 16) {
+        v += (int)dpp32<kDppXor1>((uint32_t)v);
+        v += (int)dpp32<kDppXor2>((uint32_t)v);
+        v += (int)dpp32<kDppHalfMirror>((uint32_t)v);
+        return v + (int)dpp32<kDppMirror>((uint32_t)v);
+    } else {
 #pragma unroll
-    for (int off = NM / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, NM);
-    return v;
+        for (int off = NM / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, NM);
+        return v;
+    }
 }
 
 template <int NM>
 __device__ __forceinline__ double group_dsum(double v)
 {
+    if constexpr (NM == 16) {
+        return row_sum(v);
+    } else {
 #pragma unroll
-    for (int off = NM / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, NM);
-    return v;
+        for (int off = NM / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, NM);
+        return v;
+    }
 }
 
 template <int NM>
 __device__ __forceinline__ double group_dmax(double v)
 {
+    if constexpr (NM == 16) {
+        v = fmax(v, dppd<kDppXor1>(v));
+        v = fmax(v, dppd<kDppXor2>(v));
+        v = fmax(v, dppd<kDppHalfMirror>(v));
+        return fmax(v, dppd<kDppMirror>(v));
+    } else {
 #pragma unroll
-    for (int off = NM / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, NM));
-    return v;
+        for (int off = NM / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, NM));
+        return v;
+    }
+}
+
+// z of lane Q of the caller's group (NM = 16: a DPP row broadcast)
+template <int NM, int Q>
+__device__ __forceinline__ double group_bcast(double z, int base)
+{
+    if constexpr (NM == 16)
+        return dppd<kDppRowBcast0 + Q>(z);
+    else
+        return __shfl(z, base + Q, kWave);
+}
+
+template <int Q, int NQ, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (Q < NQ) {
+        f(std::integral_constant<int, Q>{});
+        static_for<Q + 1, NQ>(f);
+    }
 }
 
 // One Gauss-Jordan pivot on dot k of [K | x]: lane `dot` holds row `dot` in
@@ -294,16 +335,20 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         // g0 = A (n0 - x_u) and U(n0) = 1/2 (n0 - x_u)^T g0 (Eq. free_energy)
         const double z = is_dot ? (double)n0 - xu : 0.0;
         double g0 = 0.0;
-#pragma unroll
-        for (int q = 0; q < NM; ++q) g0 += sA[q * kMaxDot + dot] * __shfl(z, base + q, kWave);
+        static_for<0, NM>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            g0 += sA[q * kMaxDot + dot] * group_bcast<NM, q>(z, base);
+        });
         const double u0 = 0.5 * group_dsum<NM>(z * g0);
         // terms of the lower bound of the bound-ordered scorer (open, N >= 13):
         // s = S z_hi and K = 1/2 z_hi^T s - U(n0)
         double sv = 0.0, Kb = 0.0;
         if (NM == 16 && !CLOSED && n >= 13) {
             const int hd = dot >= 8 ? dot - 8 : 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) sv += sS[hd * 8 + q] * __shfl(z, base + 8 + q, kWave);
+            static_for<0, 8>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                sv += sS[hd * 8 + q] * group_bcast<NM, (8 + q) & (NM - 1)>(z, base);
+            });
             sv = dot >= 8 ? sv : 0.0;
             Kb = 0.5 * group_dsum<NM>(z * sv) - u0;
         }
