@@ -5,6 +5,7 @@
 #include "qa_internal.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace qa {
 
@@ -378,6 +379,35 @@ __device__ __forceinline__ void prep_inverse(const double *sCdd, int n, double *
     __syncthreads();
 }
 
+// compile-time loop: f(std::integral_constant<int, Q>) for Q in [Q0, Q1)
+template <int Q0, int Q1, typename F>
+__device__ __forceinline__ void static_for_dev(F &&f)
+{
+    if constexpr (Q0 < Q1) {
+        f(std::integral_constant<int, Q0>{});
+        static_for_dev<Q0 + 1, Q1>(f);
+    }
+}
+
+// DPP row B (16 lanes) of x copied to all four rows, lane by lane: the
+// 16-lane swap pairs rows (0, 1) and (2, 3), the 32-lane swap the halves
+template <int B>
+__device__ __forceinline__ uint32_t row_bcast_block32(uint32_t x)
+{
+    const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    const uint32_t y = (B & 1) ? p[1] : p[0];
+    const auto h = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+    return (B & 2) ? h[1] : h[0];
+}
+template <int B>
+__device__ __forceinline__ double row_bcast_block(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t r = (uint64_t)row_bcast_block32<B>((uint32_t)u) |
+                       ((uint64_t)row_bcast_block32<B>((uint32_t)(u >> 32)) << 32);
+    return __longlong_as_double((long long)r);
+}
+
 // Wave 0 alone (no block barrier): the symmetric A = C_dd^{-1} into M and
 // sum|A|/2 into red[5], by the same elimination as prep_inverse.  The other
 // waves of the block may be doing anything meanwhile; the caller's next
@@ -389,42 +419,50 @@ __device__ __forceinline__ void prep_inverse(const double *sCdd, int n, double *
 __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, double *M,
                                                   double *red, double *S = nullptr)
 {
+    // lane = 16 b + j: column j of rows 4 b .. 4 b + 3 (a DPP row of the
+    // wave holds four matrix rows), so the pivot column of a lane's rows is a
+    // broadcast within its DPP row and the pivot row a broadcast of one DPP
+    // row to the others (the gfx950 row swaps); no LDS round trip per pivot
     const int tid = threadIdx.x;
-    const int i = tid >> 2, j0 = 4 * (tid & 3);
+    const int j = tid & 15, b = tid >> 4;
     double m[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int j = j0 + q;
+        const int i = 4 * b + q;
         m[q] = (i < n && j < n) ? sCdd[i * kMaxDot + j] : (i == j ? 1.0 : 0.0);
     }
+    static_for_dev<0, kMaxDot>([&](auto kc) {
+        constexpr int kk = decltype(kc)::value;
+        constexpr int k = (kk + 8) & (kMaxDot - 1);
+        if (kk == 8 && S && b >= 2 && j >= 8) {
 #pragma unroll
-    for (int kk = 0; kk < kMaxDot; ++kk) {
-        const int k = (kk + 8) & (kMaxDot - 1);
-        if (kk == 8 && S && i >= 8 && j0 >= 8) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) S[(i - 8) * 8 + j0 - 8 + q] = m[q];
+            for (int q = 0; q < 4; ++q) S[(4 * b + q - 8) * 8 + j - 8] = m[q];
         }
         if (k < n) {
-            const double mik = __shfl(m[k & 3], (i << 2) | (k >> 2));
-            const double piv = __shfl(m[k & 3], (k << 2) | (k >> 2));
-            double mk[4];
+            // M[k][j] (pivot row) and M[4 b + q][k] (pivot column)
+            const double rowk = row_bcast_block<(k >> 2)>(m[k & 3]);
+            double mik[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) mk[q] = __shfl(m[q], (k << 2) | (tid & 3));
+            for (int q = 0; q < 4; ++q) mik[q] = dppd<kDppRowBcast0 + k>(m[q]);
+            const uint64_t pu = (uint64_t)__double_as_longlong(rowk);
+            const double piv = __longlong_as_double(
+                (long long)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pu, k) |
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(pu >> 32), k)
+                             << 32)));
             const double r = 1.0 / piv;
-            const double mr = -mik * r;  // the new column k
+            const double t1 = rowk * r;
             // branch-free selects (the four cases of the pivot map)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int j = j0 + q;
-                const double t1 = mk[q] * r;
-                const double t2 = fma(-mik, t1, m[q]);
+                const int i = 4 * b + q;
+                const double t2 = fma(-mik[q], t1, m[q]);
                 const double v = (i == k) ? t1 : t2;
-                m[q] = (j == k) ? ((i == k) ? r : mr) : v;
+                m[q] = (j == k) ? ((i == k) ? r : -mik[q] * r) : v;
             }
         }
-    }
+    });
 #pragma unroll
-    for (int q = 0; q < 4; ++q) M[i * kMaxDot + j0 + q] = m[q];
+    for (int q = 0; q < 4; ++q) M[(4 * b + q) * kMaxDot + j] = m[q];
     // exactly symmetric A: each lane reads the transposed entries (LDS
     // requests of one wave are served in order, so every lane's read of the
     // first pass precedes every write of the second)
@@ -434,7 +472,7 @@ __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, dou
     double a[4], sa = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int j = j0 + q;
+        const int i = 4 * b + q;
         a[q] = (i < n && j < n) ? 0.5 * (m[q] + M[j * kMaxDot + i]) : 0.0;
         sa += fabs(a[q]);
     }
@@ -442,7 +480,7 @@ __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, dou
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int q = 0; q < 4; ++q) M[i * kMaxDot + j0 + q] = a[q];
+    for (int q = 0; q < 4; ++q) M[(4 * b + q) * kMaxDot + j] = a[q];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) sa += __shfl_xor(sa, off, 64);
     if (tid == 0) red[5] = 0.5 * sa;

@@ -15,8 +15,6 @@
 //   k_soft_bwd  its adjoint with respect to C_dd, C_gd and V.
 #include "qa_device.h"
 
-#include <type_traits>
-
 namespace qa {
 
 __global__ void k_zero_i64(int64_t *p, int n)
@@ -144,14 +142,6 @@ __device__ __forceinline__ double group_bcast(double z, int base)
         return __shfl(z, base + Q, kWave);
 }
 
-template <int Q, int NQ, typename F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    if constexpr (Q < NQ) {
-        f(std::integral_constant<int, Q>{});
-        static_for<Q + 1, NQ>(f);
-    }
-}
 
 // One Gauss-Jordan pivot on dot k of [K | x]: lane `dot` holds row `dot` in
 // r[] and its right-hand side in v; `base` is the group's first lane.
@@ -335,7 +325,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         // g0 = A (n0 - x_u) and U(n0) = 1/2 (n0 - x_u)^T g0 (Eq. free_energy)
         const double z = is_dot ? (double)n0 - xu : 0.0;
         double g0 = 0.0;
-        static_for<0, NM>([&](auto qc) {
+        static_for_dev<0, NM>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
             g0 += sA[q * kMaxDot + dot] * group_bcast<NM, q>(z, base);
         });
@@ -345,7 +335,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         double sv = 0.0, Kb = 0.0;
         if (NM == 16 && !CLOSED && n >= 13) {
             const int hd = dot >= 8 ? dot - 8 : 0;
-            static_for<0, 8>([&](auto qc) {
+            static_for_dev<0, 8>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 sv += sS[hd * 8 + q] * group_bcast<NM, (8 + q) & (NM - 1)>(z, base);
             });
