@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--batch-diagrams", type=int, default=4096)
+    ap.add_argument("--exhaustive", action="store_true",
+                    help="score every state of the box (the exhaustive matrix-core scorer)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -167,7 +169,8 @@ def main():
     d = W.grid4x4(200)
     V = torch.as_tensor(d.V, device="cuda")
     out = torch.empty((d.P, d.n_dot), dtype=torch.int32, device="cuda")
-    call = direct_gs(qa, d, V, out, args.precision, torch)
+    flags = qa.FLAG_EXHAUSTIVE if args.exhaustive else 0
+    call = direct_gs(qa, d, V, out, args.precision, torch, flags=flags)
 
     if args.mode == "adjoint":
         a = W.adjoint_case(400)
@@ -217,7 +220,8 @@ def main():
                                            ["%.4f" % s for s in stage_avg]))
 
     # stats and accuracy of the headline form against the oracle on a sample
-    n_gpu, st = qa.ground_state(d.cdd, d.cgd, V, precision=args.precision, stats=True)
+    n_gpu, st = qa.ground_state(d.cdd, d.cgd, V, precision=args.precision, stats=True,
+                                exhaustive=args.exhaustive)
     n_gpu = n_gpu.cpu().numpy()
     accuracy = {"stats": st}
     try:
@@ -250,12 +254,14 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         src = os.path.join(ROOT, "paper_2404_04994_amd", "csrc", "qa_mfma.hip")
-        if tr.get("source_sha") == sha(src) and tr.get("precision") == args.precision:
+        if (tr.get("source_sha") == sha(src) and tr.get("precision") == args.precision
+                and not args.exhaustive):
             traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "k_score_bound<%s>" % args.precision if args.precision != "fp64"
-                else "k_score_fp64<6,16>",
+                "kernel": ("k_score_fp64<6,16>" if args.precision == "fp64" else
+                           ("k_score_mfma<%s, dense>" if args.exhaustive else "k_score_bound<%s>")
+                           % args.precision),
                 "kernel_avg_us": round(stage_avg[1] * 1e3, 3),
                 "algorithmic_flops_per_launch": flops,
                 "states_scored_per_launch": st["scored"],
