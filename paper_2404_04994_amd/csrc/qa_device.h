@@ -414,8 +414,10 @@ __device__ __forceinline__ double row_bcast_block(double x)
 // block barrier publishes M.
 //
 // The pivots run over the high dots 8..n-1 first, then 0..7: after the high
-// pivots the high block of the working matrix holds (C_dd,HH)^{-1}, which is
-// copied to S (8 x 8, identity past n - 8) when S is given.
+// pivots the working matrix holds (C_dd,HH)^{-1} in its high block, the Schur
+// complement C_LL - C_LH C_HH^{-1} C_HL = (A_LL)^{-1} in its low block and
+// C_HH^{-1} C_HL in its high-low block; the whole 16 x 16 matrix is copied to
+// S when S is given (identity rows and columns past n).
 __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, double *M,
                                                   double *red, double *S = nullptr)
 {
@@ -434,9 +436,9 @@ __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, dou
     static_for_dev<0, kMaxDot>([&](auto kc) {
         constexpr int kk = decltype(kc)::value;
         constexpr int k = (kk + 8) & (kMaxDot - 1);
-        if (kk == 8 && S && b >= 2 && j >= 8) {
+        if (kk == 8 && S) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) S[(4 * b + q - 8) * 8 + j - 8] = m[q];
+            for (int q = 0; q < 4; ++q) S[(4 * b + q) * kMaxDot + j] = m[q];
         }
         if (k < n) {
             // M[k][j] (pivot row) and M[4 b + q][k] (pivot column)
@@ -518,8 +520,9 @@ __device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M,
             hl = both ? M[x * kMaxDot + y] : 0.0;
             hh = (both && x < nh && y < nh) ? M[(8 + x) * kMaxDot + 8 + y] : 0.0;
             if (S && x < nh && y < nh) {
-                hs = both ? S[x * 8 + y] : 0.0;
-                sa = fabs(S[x * 8 + y]);
+                const double sxy = S[(8 + x) * kMaxDot + 8 + y];
+                hs = both ? sxy : 0.0;
+                sa = fabs(sxy);
             }
         } else if (e < (1 << n)) {
             hl = both ? M[x * kMaxDot + y] : 0.0;
@@ -534,7 +537,19 @@ __device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M,
         if (lane == 0) {
             if (n >= 9 && S) {
                 dr->Hs[e] = (e < (1 << nh)) ? (float)(0.5 * hs) : 1e30f;
-                if (e == 0) dr->sabsS = (float)(0.5 * sa);
+                if (e == 0) {
+                    dr->sabsS = (float)(0.5 * sa);
+                    // closed-array terms: w = C_HH^{-1} C_HL 1, gamma = 1^T A_LL^{-1} 1
+                    double gam = 0.0;
+                    for (int i = 0; i < 8; ++i)
+                        for (int jj = 0; jj < 8; ++jj) gam += S[i * kMaxDot + jj];
+                    for (int jj = 0; jj < 8; ++jj) {
+                        double w = 0.0;
+                        for (int i = 0; i < 8; ++i) w += S[(8 + jj) * kMaxDot + i];
+                        dr->wB[jj] = (jj < nh) ? (float)w : 0.0f;
+                    }
+                    dr->inv2g = (float)(0.5 / gam);
+                }
             }
             if (n >= 9) {
                 dr->hlo[e] = (float)(0.5 * hl);

@@ -129,7 +129,12 @@ struct alignas(16) DiagRec {
     // 2^(N-8))
     float Hs[256];
     float sabsS;                  // sum |S_ij| / 2
-    float pad2[3];
+    // closed arrays: the low part's sum is fixed, which adds
+    // (m - mu - w^T b_hi)^2 / (2 gamma) to the bound (m = k - popc(b_hi)),
+    // w = S C_HL 1, gamma = 1^T A_LL^{-1} 1
+    float wB[8];
+    float inv2g;                  // 1 / (2 gamma)
+    float pad2[2];
 };
 
 // bytes of a DiagRec the host uploads (the inputs)
@@ -147,7 +152,7 @@ struct alignas(8) PixRec {
     // K + b_hi^T s + 1/2 b_hi^T S b_hi, s = S (n0 - x_u)_hi
     float s[8];
     float K;
-    int32_t pad1;
+    float mu;             // closed: -1^T A_LL^{-1} g_lo (the low sum of the free minimiser)
 };
 
 struct alignas(8) SavedRec {

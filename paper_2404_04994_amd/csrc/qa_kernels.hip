@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     __shared__ double sA[kMaxDot * kMaxDot];    // A (symmetric), from wave 0
     __shared__ double sc[kMaxDot];              // C_dd 1
     __shared__ double red[8];                   // [4] 1^T C_dd 1, [5] sum|A| / 2
-    __shared__ double sS[64];                   // (C_dd,HH)^{-1}, from wave 0
+    __shared__ double sS[kMaxDot * kMaxDot];    // the elimination after the high pivots, from wave 0
     __shared__ double sG[kMaxGate * NM];        // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
     // the inputs into LDS in one pass; meanwhile 16 lanes of wave 0 form
@@ -330,17 +330,25 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             g0 += sA[q * kMaxDot + dot] * group_bcast<NM, q>(z, base);
         });
         const double u0 = 0.5 * group_dsum<NM>(z * g0);
-        // terms of the lower bound of the bound-ordered scorer (open, N >= 13):
-        // s = S z_hi and K = 1/2 z_hi^T s - U(n0)
-        double sv = 0.0, Kb = 0.0;
-        if (NM == 16 && !CLOSED && n >= 13) {
-            const int hd = dot >= 8 ? dot - 8 : 0;
+        // terms of the lower bound of the bound-ordered scorer (N >= 13):
+        // s = S z_hi and K = 1/2 z_hi^T s - U(n0) with S = (C_dd,HH)^{-1};
+        // closed arrays also mu = -1^T A_LL^{-1} g0_lo
+        double sv = 0.0, Kb = 0.0, mu = 0.0;
+        if (NM == 16 && n >= 13) {
+            const int hd = dot >= 8 ? dot : 8;
             static_for_dev<0, 8>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                sv += sS[hd * 8 + q] * group_bcast<NM, (8 + q) & (NM - 1)>(z, base);
+                sv += sS[hd * kMaxDot + 8 + q] * group_bcast<NM, (8 + q) & (NM - 1)>(z, base);
             });
             sv = dot >= 8 ? sv : 0.0;
             Kb = 0.5 * group_dsum<NM>(z * sv) - u0;
+            if (CLOSED) {
+                double qrow = 0.0;
+                const int ld = dot < 8 ? dot : 0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) qrow += sS[ld * kMaxDot + q];
+                mu = -group_dsum<NM>(dot < 8 ? qrow * g0 : 0.0);
+            }
         }
 
         if (p < P) {
@@ -352,7 +360,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             if (dot >= 8) o->s[dot - 8] = (float)sv;
             if (dot == 0) {
                 o->K = (float)Kb;
-                o->pad1 = 0;
+                o->mu = (float)mu;
                 o->u0 = u0;
                 o->free = fm;
                 o->k = k;

@@ -552,12 +552,14 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
 // the dense scorer over the scored rows.  The result is the argmin over the
 // whole box, as in the dense form.
 // ---------------------------------------------------------------------------
-template <int PREC>
+template <int PREC, int MODE>
 __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const DiagRec *__restrict__ dr,
                                                      const PixRec *__restrict__ pr, int64_t P,
                                                      int32_t *__restrict__ n_out,
                                                      int64_t *__restrict__ counters)
 {
+    constexpr bool PRUNED = MODE != kDense;
+    constexpr bool CLOSED = MODE == kClosed;
     __shared__ float sT1[16][8];
     __shared__ float sT2[16][8];
     __shared__ float sH[256];
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
     __shared__ double sG64[4][kMaxDot];
     __shared__ uint2 sCt[4][256];                // per wave: C(c_hi) of its pixel (BF16 parts / FP32)
     __shared__ uint8_t sList[4][256];            // per wave: high index of every scored row
-    __shared__ unsigned long long sflag, sgap, srows;
+    __shared__ unsigned long long sflag, sgap, srows, scand;
     const int n = dr->n;
     const int nh = n - 8;
     const int nrt = 1 << (nh - 4);
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         sLd[e] = dr->hlod[e];
         sHs[e] = dr->Hs[e];
     }
-    if (threadIdx.x == 0) { sflag = 0; sgap = 0; srows = 0; }
+    if (threadIdx.x == 0) { sflag = 0; sgap = 0; srows = 0; scand = 0; }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -592,6 +594,15 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
     const int li = lane & 15;
     const float sumabs = dr->sumabs;
     const float hsabs = dr->sabsS;
+    // closed arrays: w and 1 / (2 gamma) of the low-sum term of the bound
+    float wb[8];
+    float wabs = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        wb[j] = CLOSED ? dr->wB[j] : 0.0f;
+        wabs += fabsf(wb[j]);
+    }
+    const float inv2g = CLOSED ? dr->inv2g : 0.0f;
 
     // pixel-independent column operands (as in the dense scorer)
     uint32_t bw[16][4];
@@ -635,36 +646,61 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
 
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    int64_t nflag = 0, ngap = 0, nrows = 0;
+    int64_t nflag = 0, ngap = 0, nrows = 0, ncand = 0;
     uint2 *ctab = sCt[wv];
     uint8_t *list = sList[wv];
     double *g64 = sG64[wv];
-    // lane i < 16 holds g0_i and n0_i, lanes 8..15 also s_{i-8}, lane 0 K
-    // (vector loads, one pixel ahead)
+    // lane i < 16 holds g0_i and n0_i, lanes 8..15 also s_{i-8}, lane 0 K,
+    // lane 1 mu (vector loads, one pixel ahead)
     double gnext = 0.0;
-    int nnext = 0;
+    int nnext = 0, knext = 0;
+    uint32_t fnext = 0;
     float snext = 0.0f;
     if (wave < P) {
         gnext = pr[wave].g0[li];
         nnext = pr[wave].n0[li];
-        snext = (li >= 8) ? pr[wave].s[li - 8] : pr[wave].K;
+        snext = (li >= 8) ? pr[wave].s[li - 8] : (li == 1 ? pr[wave].mu : pr[wave].K);
+        if (PRUNED) fnext = pr[wave].free;
+        if (CLOSED) knext = pr[wave].k;
     }
     for (int64_t p = wave; p < P; p += nwaves) {
         const double gcur = gnext;
         const int ncur = nnext;
         const float scur = snext;
+        // free dots and raised count of the pixel (wave-uniform)
+        const uint32_t F = PRUNED ? __builtin_amdgcn_readfirstlane(fnext) : 0xFFFFu;
+        const int kc = CLOSED ? __builtin_amdgcn_readfirstlane(knext) : 0;
         if (p + nwaves < P) {
             gnext = pr[p + nwaves].g0[li];
             nnext = pr[p + nwaves].n0[li];
-            snext = (li >= 8) ? pr[p + nwaves].s[li - 8] : pr[p + nwaves].K;
+            snext = (li >= 8) ? pr[p + nwaves].s[li - 8]
+                              : (li == 1 ? pr[p + nwaves].mu : pr[p + nwaves].K);
+            if (PRUNED) fnext = pr[p + nwaves].free;
+            if (CLOSED) knext = pr[p + nwaves].k;
         }
+        // g0 beyond n is zero in the record.  Thresholded and closed sets: a
+        // fixed dot's entry carries the penalty 2^100 (states raising it never
+        // win; the others score as in the dense form), the error bound takes
+        // the unpenalised values.
         const float gl = (float)gcur;
+        const float glp = (PRUNED && !(F >> li & 1u)) ? 0x1p100f : gl;
         float g[16];
         float gabs = 0.0f;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i));
-            gabs += fabsf(g[i]);
+            g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(glp), i));
+            gabs += fabsf(PRUNED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i))
+                                 : g[i]);
+        }
+        const uint32_t Fhi = (F >> 8) & 0xFFu;
+        const int nflo = __popc(F & 0xFFu);
+        if (MODE == kPruned) ncand += 1ll << __popc(F & ((1u << n) - 1u));
+        if (CLOSED) {
+            // C(free dots, k)
+            const int nf = __popc(F & ((1u << n) - 1u));
+            int64_t bc = 1;
+            for (int j = 0; j < kc && j < nf; ++j) bc = bc * (nf - j) / (j + 1);
+            ncand += (kc >= 0 && kc <= nf) ? bc : 0;
         }
         // ---- the bound terms of the setup: s = S (n0 - x_u)_hi and K ----
         if (lane < kMaxDot) g64[lane] = gcur;  // FP64 g of the near-tie re-score
@@ -676,37 +712,56 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
             sabs += fabsf(sb[i]);
         }
         const float Kf = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scur), 0));
+        const float muf = CLOSED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scur), 1))
+                                 : 0.0f;
         // Certified bound on |E_approx - E| (as in the dense scorer), and the
         // FP32 error of the bound: at most a dozen roundings of partial sums
         // that are bounded by |K| + sum|s| + 1/2 sum|S|; 2^-19 of that covers
         // them with room to spare.
         const float S = gabs + sumabs;
         const float delta = (PREC == kPrecX2 ? 0x1p-15f : 0x1p-17f) * S;
-        const float margin = 4.0f * delta + 0x1p-19f * (fabsf(Kf) + sabs + hsabs);
+        // closed: the low-sum term (m - mu - w^T b_hi)^2 / (2 gamma) adds the
+        // FP32 error of a square of terms bounded by 8 + |mu| + sum|w|
+        const float lsum = 8.0f + fabsf(muf) + wabs;
+        const float margin = 4.0f * delta + 0x1p-19f * (fabsf(Kf) + sabs + hsabs) +
+                             (CLOSED ? 0x1p-19f * lsum * lsum * inv2g : 0.0f);
 
         // ---- per lane: bound and constant chunk of high indices (q + 4 e) * 16 + row ----
-        float P1 = 0.0f, R1 = 0.0f;
+        float P1 = 0.0f, R1 = 0.0f, W1 = 0.0f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (mrow >> j & 1) {
                 P1 += g[8 + j];
                 R1 += sb[j];
+                W1 += wb[j];
             }
         }
         float lb[4];
 #pragma unroll
         for (int e4 = 0; e4 < 4; ++e4) {
             const int rt = q + 4 * e4;
-            float P2 = 0.0f, R2 = 0.0f;
+            float P2 = 0.0f, R2 = 0.0f, W2 = 0.0f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (rt >> j & 1) {
                     P2 += g[12 + j];
                     R2 += sb[4 + j];
+                    W2 += wb[4 + j];
                 }
             }
             const int chi = rt * 16 + mrow;
-            lb[e4] = (rt < nrt) ? ((Kf + R1) + R2) + sHs[chi] : INFINITY;
+            float L = ((Kf + R1) + R2) + sHs[chi];
+            bool ok = rt < nrt;
+            if (PRUNED) ok = ok && !((uint32_t)chi & ~Fhi);  // raises a fixed high dot
+            if (CLOSED) {
+                // m raised low dots: none of this high part's states is admissible
+                // unless 0 <= m <= free low dots
+                const int m = kc - __popc((uint32_t)chi);
+                const float dm = ((float)m - muf) - (W1 + W2);
+                L += dm * dm * inv2g;
+                ok = ok && m >= 0 && m <= nflo;
+            }
+            lb[e4] = ok ? L : INFINITY;
             const float C = (P1 + P2) + sH[chi];
             if (PREC == kPrecFP32) {
                 ctab[chi] = make_uint2(fbits(C), 0u);
@@ -745,6 +800,26 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         if (PREC == kPrecFP32) gb = (q == 0) ? g[4] : gb;
         int cnt = 16;  // scored rows so far (wave-uniform)
 
+        auto ct_ok = [&](int ct) { return !PRUNED || !(((uint32_t)ct << 4) & ~F & 0xF0u); };
+        // closed: popcounts of this lane's four elements of tile t less that of
+        // the column tile (rows 4q..4q+3, column bits mrow)
+        auto elem_pc = [&](int t, int (&eq)[4]) {
+            if (CLOSED) {
+                const uint32_t r4 = *reinterpret_cast<const uint32_t *>(&list[t * 16 + 4 * q]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    eq[i] = __popc((r4 >> (8 * i)) & 0xFFu) + __popc((uint32_t)mrow);
+            }
+        };
+        // closed: elements whose state does not raise exactly k dots are +inf
+        auto qualify = [&](f32x4_t d, const int (&eq)[4], int ct) -> f32x4_t {
+            if (CLOSED) {
+                const int r = kc - __popc((uint32_t)ct);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d[i] = (eq[i] == r) ? d[i] : INFINITY;
+            }
+            return d;
+        };
         // A operand of tile t: row r of the tile is high index list[16 t + r]
         // (unused rows past cnt get the sentinel constant chunk)
         auto build_rows = [&](int t, Pack8 &a, float (&af)[3]) {
@@ -818,11 +893,23 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         auto score_tile = [&](int t) {
             Pack8 a;
             float af[3];
+            int eq[4];
             build_rows(t, a, af);
-            f32x4_t dp = tile(a, af, 0);
+            elem_pc(t, eq);
+            if (PRUNED) {
+                // column tiles that raise a fixed dot of 4..7 hold no candidate
+#pragma unroll
+                for (int ct = 0; ct < 16; ++ct) {
+                    if (!ct_ok(ct)) continue;
+                    track(qualify(tile(a, af, ct), eq, ct), t * 16 + ct);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                return;
+            }
+            f32x4_t dp = qualify(tile(a, af, 0), eq, 0);
 #pragma unroll
             for (int ct = 1; ct < 16; ++ct) {
-                const f32x4_t d = tile(a, af, ct);
+                const f32x4_t d = qualify(tile(a, af, ct), eq, ct);
                 track(dp, t * 16 + ct - 1);
                 dp = d;
                 __builtin_amdgcn_sched_barrier(0);
@@ -863,11 +950,13 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         {
             Pack8 a;
             float af[3];
+            int eq[4];
             build_rows(tw, a, af);
+            elem_pc(tw, eq);
             f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct)
-                if (ct == ctw) d = tile(a, af, ct);
+                if (ct == ctw) d = qualify(tile(a, af, ct), eq, ct);
             float v1 = d[0], v2 = INFINITY;
             int i1 = 0;
 #pragma unroll
@@ -899,11 +988,14 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         for (int t = 0; t < ntiles; ++t) {
             Pack8 a;
             float af[3];
+            int eq[4];
             build_rows(t, a, af);
+            elem_pc(t, eq);
             uint32_t ib[2] = {0u, 0u};  // bit 4 ct + i: element i of tile ct
 #pragma unroll
             for (int ct = 0; ct < 16; ++ct) {
-                const f32x4_t d = tile(a, af, ct);
+                if (!ct_ok(ct)) continue;
+                const f32x4_t d = qualify(tile(a, af, ct), eq, ct);
                 const float dm = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
                 if (dm <= thr) {
                     uint32_t m4 = 0u;
@@ -976,13 +1068,15 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         if (nflag) atomicAdd(&sflag, (unsigned long long)nflag);
         if (ngap) atomicAdd(&sgap, (unsigned long long)ngap);
         if (nrows) atomicAdd(&srows, (unsigned long long)nrows);
+        if (ncand) atomicAdd(&scand, (unsigned long long)ncand);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         block_add_counter(counters, C_NEAR_TIE, (int64_t)sflag);
         block_add_counter(counters, C_GAP_1E9, (int64_t)sgap);
         block_add_counter(counters, C_SCORED, (int64_t)srows << 8);  // 256 states per row
-        if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
+        if (PRUNED) block_add_counter(counters, C_CANDIDATES, (int64_t)scand);  // summed per pixel
+        else if (blockIdx.x == 0) block_add_counter(counters, C_CANDIDATES, P << n);
     }
 }
 
@@ -991,9 +1085,9 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
 template <typename Kernel>
 static int resident_blocks(Kernel kernel, int slot)
 {
-    static int cache[16][64];
+    static int cache[24][64];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || slot < 0 || slot >= 16) return 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || slot < 0 || slot >= 24) return 0;
     int &c = cache[slot][dev];
     if (c) return c;
     int cus = 0, per_cu = 0;
@@ -1026,13 +1120,20 @@ hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int
 {
     if (n_dot < 9 || n_dot > 16 || mode < kDense || mode > kClosed) return hipErrorInvalidValue;
     if (P <= 0) return hipSuccess;
-    if (mode == kDense && n_dot >= 13 && !exhaustive) {
-        if (prec == kPrecFP32)
-            return launch_persistent(k_score_bound<kPrecFP32>, 9, dr, pr, P, n_out, counters, s);
-        if (prec == kPrecX3)
-            return launch_persistent(k_score_bound<kPrecX3>, 10, dr, pr, P, n_out, counters, s);
-        if (prec == kPrecX2)
-            return launch_persistent(k_score_bound<kPrecX2>, 11, dr, pr, P, n_out, counters, s);
+    if (n_dot >= 13 && !exhaustive) {
+#define QA_BOUND_CASE(PR, MD, SLOT)                                                             \
+    if (prec == PR && mode == MD)                                                               \
+        return launch_persistent(k_score_bound<PR, MD>, SLOT, dr, pr, P, n_out, counters, s);
+        QA_BOUND_CASE(kPrecFP32, kDense, 9)
+        QA_BOUND_CASE(kPrecX3, kDense, 10)
+        QA_BOUND_CASE(kPrecX2, kDense, 11)
+        QA_BOUND_CASE(kPrecFP32, kPruned, 12)
+        QA_BOUND_CASE(kPrecX3, kPruned, 13)
+        QA_BOUND_CASE(kPrecX2, kPruned, 14)
+        QA_BOUND_CASE(kPrecFP32, kClosed, 15)
+        QA_BOUND_CASE(kPrecX3, kClosed, 16)
+        QA_BOUND_CASE(kPrecX2, kClosed, 17)
+#undef QA_BOUND_CASE
         return hipErrorInvalidValue;
     }
 #define QA_SCORER_CASE(PR, MD, SLOT)                                                            \

@@ -215,3 +215,33 @@ def test_bound_order_paper_replica(qa, oracle, n_dot, seed):
     assert st["scored"] < st["candidates"]
     compare(qa, oracle, d, "fp32")
     compare(qa, oracle, d, "bf16x2")
+
+
+@pytest.mark.parametrize("case", ["closed20", "closed_replica", "t0.5", "t0.333", "closed_t0.5"])
+def test_bound_order_closed_and_thresholded_equal_exhaustive(qa, case):
+    """Bound-ordered search of the thresholded sub-boxes and of the closed
+    subsets (the closed bound adds the fixed low-part sum): at every pixel the
+    exhaustive scorer's state, with fewer energies computed."""
+    if case == "closed_replica":
+        d = W.paper_replica(16, seed=730, npix=60, closed=True)
+        kw = dict(closed=True, nhat=16)
+    else:
+        d = W.grid4x4(208, npix=60)
+        kw = {}
+        if case.startswith("closed"):
+            kw = dict(closed=True, nhat=20)
+        if "t0." in case:
+            kw["t"] = float(case.split("t")[-1])
+    V = torch.as_tensor(d.V).cuda()
+    for prec in PRECS:
+        nb, sb = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, **kw)
+        ne, se = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, exhaustive=True,
+                                 **kw)
+        diff = (nb.cpu().numpy() != ne.cpu().numpy()).any(1).sum()
+        say("%s %s: scored %d (exhaustive %d) of %d candidates, near ties %d / %d, diff %d"
+            % (case, prec, sb["scored"], se["scored"], sb["candidates"], sb["near_tie_pixels"],
+               se["near_tie_pixels"], diff))
+        assert diff == 0
+        assert sb["candidates"] == se["candidates"]
+        if kw.get("closed"):
+            assert (nb.cpu().numpy().sum(1) == kw["nhat"]).all()
