@@ -504,13 +504,17 @@ __device__ __forceinline__ void prep_store_core(DiagRec *dr, const double *M, co
 // The energy tables from A in LDS, spread over the waves of a grid: entry e
 // (of 256) goes to global wave e mod (number of waves), whose 64 lanes take
 // the 8 x 8 products b_x b_y A_xy and sum them.
+//
+// With first/stride the caller picks the entries of this wave (default: the
+// global wave index and the number of waves of the grid).
 __device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M,
-                                                   const double *S = nullptr)
+                                                   const double *S = nullptr, int first = -1,
+                                                   int stride = 0)
 {
     const int n = dr->n;
     const int lane = threadIdx.x & (kWave - 1);
-    const int gw = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int nw = gridDim.x * (blockDim.x / kWave);
+    const int gw = first >= 0 ? first : blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int nw = first >= 0 ? stride : gridDim.x * (blockDim.x / kWave);
     const int x = lane >> 3, y = lane & 7;
     const int nh = n - 8;
     for (int e = gw; e < 256; e += nw) {
@@ -527,12 +531,11 @@ __device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M,
         } else if (e < (1 << n)) {
             hl = both ? M[x * kMaxDot + y] : 0.0;
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            hl += __shfl_xor(hl, off, kWave);
-            hh += __shfl_xor(hh, off, kWave);
-            hs += __shfl_xor(hs, off, kWave);
-            sa += __shfl_xor(sa, off, kWave);
+        hl = wave_sum(hl);
+        hh = wave_sum(hh);
+        if (S && n >= 9) {
+            hs = wave_sum(hs);
+            if (e == 0) sa = wave_sum(sa);
         }
         if (lane == 0) {
             if (n >= 9 && S) {

@@ -100,6 +100,21 @@ __device__ __forceinline__ float rows_min(float x)
     return fminf(__uint_as_float(t[0]), __uint_as_float(t[1]));
 }
 __device__ __forceinline__ float wave_min(float x) { return rows_min(row_min(x)); }
+// sum over the 64 lanes (every lane gets it): the row sums, then the row swaps
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x = row_sum(x);
+    auto swap_add = [&](auto swap) {
+        const uint64_t u = (uint64_t)__double_as_longlong(x);
+        const auto lo = swap((uint32_t)u), hi = swap((uint32_t)(u >> 32));
+        const double a = __longlong_as_double((long long)((uint64_t)lo[0] | ((uint64_t)hi[0] << 32)));
+        const double b = __longlong_as_double((long long)((uint64_t)lo[1] | ((uint64_t)hi[1] << 32)));
+        x = a + b;
+    };
+    swap_add([](uint32_t v) { return __builtin_amdgcn_permlane16_swap(v, v, false, false); });
+    swap_add([](uint32_t v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false); });
+    return x;
+}
 
 struct alignas(16) DiagRec {
     // inputs (written by the host, or by k_prep_batch): everything up to Cgd

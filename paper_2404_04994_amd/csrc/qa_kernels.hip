@@ -238,6 +238,14 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         __builtin_amdgcn_s_setprio(3);
         prep_inverse_wave(sCdd, n, sA, red, sS);
         __builtin_amdgcn_s_setprio(0);
+        // a grid of at least 256 blocks: wave 0 of block b fills energy-table
+        // entry b while the pixel waves finish (off the kernel's tail)
+        if (gridDim.x >= 256) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            prep_tables_spread(dr, sA, sS, (int)blockIdx.x, (int)gridDim.x);
+        }
     } else {
         // x_u = C_gd V
         for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * V[pc * g + j];
@@ -381,13 +389,14 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     if (threadIdx.x < 4) bstats[blockIdx.x * 4 + threadIdx.x] = cnt[threadIdx.x];
     // the diagram's record for the next kernels: block 0 stores A and the
     // sums and clears the call's counters; the table entries are spread
-    // over the waves of the grid
+    // over the waves of the grid (small grids) or were filled by wave 0
+    // of the first 256 blocks
     if (blockIdx.x == 0) {
         prep_store_core(dr, sA, sc, red);
         if (counters)
             for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x) counters[i] = 0;
     }
-    prep_tables_spread(dr, sA, sS);
+    if (gridDim.x < 256) prep_tables_spread(dr, sA, sS);
 }
 
 #define QA_DISPATCH_NM(n, CALL)                        \
