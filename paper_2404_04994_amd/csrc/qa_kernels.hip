@@ -233,6 +233,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     double xu = 0.0, x = 0.0;
     int n0 = 0, k = -1, flags = 0, cflags = 0;
     uint32_t fm = 0;
+    uint32_t gm = 0;  // rounding of x* inside the candidate set
     if (!pixel_wave) {
         // the inverse is the block's critical path: its wave issues first
         __builtin_amdgcn_s_setprio(3);
@@ -326,6 +327,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             cflags |= 4;
         }
         fm = group_ballot<NM>(freed);
+        gm = group_ballot<NM>(freed && x - (double)n0 >= 0.5);
     }
     __syncthreads();  // A from wave 0
 
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
                 o->free = fm;
                 o->k = k;
                 o->flags = flags | cflags;
-                o->pad = 0;
+                o->guess = gm;
                 if (flags_out) flags_out[p] = flags | (cflags & 4);
                 if (cflags & 4) atomicAdd(&cnt[2], 1);
                 if (flags & 1) atomicAdd(&cnt[1], 1);

@@ -563,6 +563,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
     __shared__ float sT1[16][8];
     __shared__ float sT2[16][8];
     __shared__ float sH[256];
+    __shared__ float sHlo[256];                  // 1/2 b_lo^T A_LL b_lo
     __shared__ float sHs[256];                   // 1/2 b_hi^T S b_hi (1e30 beyond 2^(N-8))
     __shared__ double sT1d[16][8], sT2d[16][8];  // FP64 tables of the near-tie re-score
     __shared__ double sHd[256], sLd[256];
@@ -584,6 +585,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         sHd[e] = dr->Hhid[e];
         sLd[e] = dr->hlod[e];
         sHs[e] = dr->Hs[e];
+        sHlo[e] = dr->hlo[e];
     }
     if (threadIdx.x == 0) { sflag = 0; sgap = 0; srows = 0; scand = 0; }
     __syncthreads();
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
     // lane 1 mu (vector loads, one pixel ahead)
     double gnext = 0.0;
     int nnext = 0, knext = 0;
-    uint32_t fnext = 0;
+    uint32_t fnext = 0, gsnext = 0;
     float snext = 0.0f;
     if (wave < P) {
         gnext = pr[wave].g0[li];
@@ -662,6 +664,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         snext = (li >= 8) ? pr[wave].s[li - 8] : (li == 1 ? pr[wave].mu : pr[wave].K);
         if (PRUNED) fnext = pr[wave].free;
         if (CLOSED) knext = pr[wave].k;
+        else gsnext = pr[wave].guess;
     }
     for (int64_t p = wave; p < P; p += nwaves) {
         const double gcur = gnext;
@@ -670,6 +673,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         // free dots and raised count of the pixel (wave-uniform)
         const uint32_t F = PRUNED ? __builtin_amdgcn_readfirstlane(fnext) : 0xFFFFu;
         const int kc = CLOSED ? __builtin_amdgcn_readfirstlane(knext) : 0;
+        const uint32_t gsb = CLOSED ? 0u : __builtin_amdgcn_readfirstlane(gsnext);
         if (p + nwaves < P) {
             gnext = pr[p + nwaves].g0[li];
             nnext = pr[p + nwaves].n0[li];
@@ -677,6 +681,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                               : (li == 1 ? pr[p + nwaves].mu : pr[p + nwaves].K);
             if (PRUNED) fnext = pr[p + nwaves].free;
             if (CLOSED) knext = pr[p + nwaves].k;
+            else gsnext = pr[p + nwaves].guess;
         }
         // g0 beyond n is zero in the record.  Thresholded and closed sets: a
         // fixed dot's entry carries the penalty 2^100 (states raising it never
@@ -772,21 +777,69 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                 ctab[chi] = make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
             }
         }
-        // row tile with the smallest bound
-        float rlb[4];
+        // The rows to score.  Open arrays: the setup's rounding of x* is a
+        // state of the candidate set; its energy E_g (FP32 from the tables,
+        // error below delta / 5) bounds the approximate best from above
+        // (by E_g + 1.2 delta), so a high part whose bound exceeds
+        // E_g + margin + delta holds neither the argmin nor a near-tie state.
+        // When at most two tiles' worth of high parts pass that test they are
+        // the rows (most pixels); otherwise, and for closed arrays, the row
+        // tile with the smallest bound is scored first and the high parts
+        // within the margin of its best (and under the first threshold) follow.
+        int rts = -1;
+        int cnt = 0;  // scored rows (wave-uniform)
+        auto list_rows = [&](float thr, int skip_rt) {
 #pragma unroll
-        for (int e4 = 0; e4 < 4; ++e4) rlb[e4] = row_min(lb[e4]);
-        float mb = rlb[0];
-        int me = 0;
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int rt = q + 4 * e4;
+                const bool take = lb[e4] <= thr && rt != skip_rt;
+                const unsigned long long m = __ballot(take);
+                if (take)
+                    list[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0))] =
+                        (uint8_t)(rt * 16 + mrow);
+                cnt += __popcll(m);
+            }
+        };
+        float thr_g = INFINITY;
+        bool by_guess = false;
+        if (!CLOSED) {
+            const int chg = (int)(gsb >> 8), clg = (int)(gsb & 0xFFu);
+            const int rowg = chg & 15, rtg = chg >> 4;
+            float P1g = 0.0f, P2g = 0.0f;
 #pragma unroll
-        for (int e4 = 1; e4 < 4; ++e4)
-            if (rlb[e4] < mb) { mb = rlb[e4]; me = e4; }
-        const float gmb = rows_min(mb);
-        const unsigned long long hb = __ballot(mb == gmb);
-        const int wl = __ffsll((long long)hb) - 1;
-        const int rts = __builtin_amdgcn_readlane(q + 4 * me, wl);
-        if (lane < 16) list[lane] = (uint8_t)(rts * 16 + lane);
-        wave_sync();  // the constant chunks and the first tile's rows
+            for (int j = 0; j < 4; ++j) {
+                if (rowg >> j & 1) P1g += g[8 + j];
+                if (rtg >> j & 1) P2g += g[12 + j];
+            }
+            float Eg = ((P1g + P2g) + sH[chg]) + sHlo[clg];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (clg >> i & 1) Eg += (g[i] + sT1[rowg][i]) + sT2[rtg][i];
+            thr_g = Eg + margin + delta;
+            int ng = 0;
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) ng += __popcll(__ballot(lb[e4] <= thr_g));
+            by_guess = ng <= 32;
+            if (by_guess) list_rows(thr_g, -1);
+        }
+        if (!by_guess) {
+            float rlb[4];
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) rlb[e4] = row_min(lb[e4]);
+            float mb = rlb[0];
+            int me = 0;
+#pragma unroll
+            for (int e4 = 1; e4 < 4; ++e4)
+                if (rlb[e4] < mb) { mb = rlb[e4]; me = e4; }
+            const float gmb = rows_min(mb);
+            const unsigned long long hb = __ballot(mb == gmb);
+            const int wl = __ffsll((long long)hb) - 1;
+            rts = __builtin_amdgcn_readlane(q + 4 * me, wl);
+            if (lane < 16) list[lane] = (uint8_t)(rts * 16 + lane);
+            cnt = 16;
+        }
+        wave_sync();  // the constant chunks and the first rows
 
         // g_{2q}, g_{2q+1} (split-BF16 forms) or g_q, g_{4+q} (FP32) of this lane
         float ga = g[0], gb = g[1];
@@ -798,7 +851,6 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
             }
         }
         if (PREC == kPrecFP32) gb = (q == 0) ? g[4] : gb;
-        int cnt = 16;  // scored rows so far (wave-uniform)
 
         auto ct_ok = [&](int ct) { return !PRUNED || !(((uint32_t)ct << 4) & ~F & 0xF0u); };
         // closed: popcounts of this lane's four elements of tile t less that of
@@ -916,26 +968,15 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
             }
             track(dp, t * 16 + 15);
         };
-        score_tile(0);
-        // the other high indices whose bound admits a state within the margin
-        // of the best so far, compacted into the list
-        {
-            const float thr = wave_min(b1) + margin;
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                const int rt = q + 4 * e4;
-                const bool take = lb[e4] <= thr && rt != rts;
-                const unsigned long long m = __ballot(take);
-                if (take)
-                    list[cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0))] =
-                        (uint8_t)(rt * 16 + mrow);
-                cnt += __popcll(m);
-            }
+        if (!by_guess) {
+            score_tile(0);
+            // the other high indices whose bound admits a state within the
+            // margin of the best so far
+            list_rows(fminf(wave_min(b1) + margin, thr_g), rts);
             wave_sync();
         }
         const int ntiles = (cnt + 15) >> 4;
-        for (int t = 1; t < ntiles; ++t) score_tile(t);
+        for (int t = by_guess ? 0 : 1; t < ntiles; ++t) score_tile(t);
         nrows += cnt;
 
         // ---- best over the wave, runner-up bound, winner's tile once more ----
