@@ -327,7 +327,20 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             cflags |= 4;
         }
         fm = group_ballot<NM>(freed);
-        gm = group_ballot<NM>(freed && x - (double)n0 >= 0.5);
+        if (!CLOSED) {
+            gm = group_ballot<NM>(freed && x - (double)n0 >= 0.5);
+        } else if (NM == 16) {
+            // closed: the k free dots with the largest fractional parts (ties
+            // to the lower index), an admissible state of the candidate set
+            const double fr = freed ? x - (double)n0 : -1.0;
+            int rank = 0;
+            static_for_dev<0, NM>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                const double fq = group_bcast<NM, q>(fr, base);
+                rank += ((fm >> q & 1u) && (fq > fr || (fq == fr && q < dot))) ? 1 : 0;
+            });
+            gm = group_ballot<NM>(freed && rank < k);
+        }
     }
     __syncthreads();  // A from wave 0
 

@@ -664,7 +664,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         snext = (li >= 8) ? pr[wave].s[li - 8] : (li == 1 ? pr[wave].mu : pr[wave].K);
         if (PRUNED) fnext = pr[wave].free;
         if (CLOSED) knext = pr[wave].k;
-        else gsnext = pr[wave].guess;
+        gsnext = pr[wave].guess;
     }
     for (int64_t p = wave; p < P; p += nwaves) {
         const double gcur = gnext;
@@ -673,7 +673,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         // free dots and raised count of the pixel (wave-uniform)
         const uint32_t F = PRUNED ? __builtin_amdgcn_readfirstlane(fnext) : 0xFFFFu;
         const int kc = CLOSED ? __builtin_amdgcn_readfirstlane(knext) : 0;
-        const uint32_t gsb = CLOSED ? 0u : __builtin_amdgcn_readfirstlane(gsnext);
+        const uint32_t gsb = __builtin_amdgcn_readfirstlane(gsnext);
         if (p + nwaves < P) {
             gnext = pr[p + nwaves].g0[li];
             nnext = pr[p + nwaves].n0[li];
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                               : (li == 1 ? pr[p + nwaves].mu : pr[p + nwaves].K);
             if (PRUNED) fnext = pr[p + nwaves].free;
             if (CLOSED) knext = pr[p + nwaves].k;
-            else gsnext = pr[p + nwaves].guess;
+            gsnext = pr[p + nwaves].guess;
         }
         // g0 beyond n is zero in the record.  Thresholded and closed sets: a
         // fixed dot's entry carries the penalty 2^100 (states raising it never
@@ -777,15 +777,16 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                 ctab[chi] = make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
             }
         }
-        // The rows to score.  Open arrays: the setup's rounding of x* is a
-        // state of the candidate set; its energy E_g (FP32 from the tables,
-        // error below delta / 5) bounds the approximate best from above
-        // (by E_g + 1.2 delta), so a high part whose bound exceeds
+        // The rows to score.  The setup's guess (the rounding of x*; closed:
+        // the k free dots with the largest fractional parts) is a state of
+        // the candidate set; its energy E_g (FP32 from the tables, error
+        // below delta / 5) bounds the approximate best from above (by
+        // E_g + 1.2 delta), so a high part whose bound exceeds
         // E_g + margin + delta holds neither the argmin nor a near-tie state.
         // When at most two tiles' worth of high parts pass that test they are
-        // the rows (most pixels); otherwise, and for closed arrays, the row
-        // tile with the smallest bound is scored first and the high parts
-        // within the margin of its best (and under the first threshold) follow.
+        // the rows (most pixels); otherwise the row tile with the smallest
+        // bound is scored first and the high parts within the margin of its
+        // best (and under the first threshold) follow.
         int rts = -1;
         int cnt = 0;  // scored rows (wave-uniform)
         auto list_rows = [&](float thr, int skip_rt) {
@@ -803,7 +804,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         };
         float thr_g = INFINITY;
         bool by_guess = false;
-        if (!CLOSED) {
+        {
             const int chg = (int)(gsb >> 8), clg = (int)(gsb & 0xFFu);
             const int rowg = chg & 15, rtg = chg >> 4;
             float P1g = 0.0f, P2g = 0.0f;
