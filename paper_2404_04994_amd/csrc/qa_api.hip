@@ -84,6 +84,13 @@ struct Workspace {
     int stage_next = 0;
     // the inputs last copied into dr (a call with the same problem reuses them)
     std::vector<unsigned char> dr_inputs;
+    // w->dr also holds the prologue's outputs (A, sums, tables) for the
+    // inputs in dr_inputs: a setup or prologue launch has been enqueued since
+    // they were uploaded
+    bool dr_derived = false;
+    // the adjoint's accumulators are zero (the final adjoint kernel leaves
+    // them so; fresh allocations are cleared once)
+    bool acc_zero = false;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
 };
 
@@ -257,6 +264,7 @@ qa_status upload_diag(Workspace *w, const qa_problem *pb)
     QA_HIP(hipMemcpyAsync(w->dr, &w->stage[slot], kDiagInputBytes, hipMemcpyHostToDevice,
                           w->stream));
     QA_HIP(hipEventRecord(w->stage_ev[slot], w->stream));
+    w->dr_derived = false;
     const unsigned char *b = reinterpret_cast<const unsigned char *>(&w->stage[slot]);
     w->dr_inputs.assign(b, b + kDiagInputBytes);
     return QA_OK;
@@ -296,6 +304,7 @@ qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, cons
     const bool closed = pb->mode == QA_CLOSED;
     if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
     QA_HIP(launch_setup(w->dr, V, P, w->pr, w->counters, w->bstats, pb->n_dot, closed, s));
+    w->dr_derived = true;
     if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
     if (nbar) {
         QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
@@ -481,15 +490,26 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
     if (w->dr != dr0) w->dr_inputs.clear();
     const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + 4096;
+    double *acc0 = w->acc;
     if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
+    if (w->acc != acc0) w->acc_zero = false;
     if ((st = upload_diag(w, prob))) return st;
     double *accA = w->acc, *accG = accA + kMaxDot * kMaxDot, *accU = accG + kMaxDot * kMaxGate;
-    QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream, accA,
-                       (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate +
-                           ((int64_t)1 << prob->n_dot)));
+    // the prologue (A, C_dd 1, tables) only when the record does not already
+    // hold it for these inputs (the usual case after the forward call);
+    // it also clears the accumulators when they are not known to be zero
+    const int64_t nzero = w->acc_zero ? 0 : nacc;
+    if (!w->dr_derived) {
+        QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream, nzero ? accA : nullptr, nzero));
+        w->dr_derived = true;
+    } else if (nzero) {
+        QA_HIP(launch_zero_i64(reinterpret_cast<int64_t *>(accA), (int)nzero, w->stream));
+    }
+    w->acc_zero = false;  // until the final kernel below is enqueued
     QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, accA, accG,
                            accU, grad_V_dev, prob->n_dot, w->stream));
     QA_HIP(launch_soft_bwd_final(w->dr, accA, accG, accU, grad_cdd_dev, grad_cgd_dev, w->stream));
+    w->acc_zero = true;
     return QA_OK;
 }
 

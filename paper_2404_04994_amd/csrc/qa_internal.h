@@ -230,8 +230,8 @@ hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P,
                            const double *gbar, const SavedRec *saved, double *accA,
                            double *accG, double *accU, double *gradV, int n_dot,
                            hipStream_t s);
-hipError_t launch_soft_bwd_final(const DiagRec *dr, const double *accA, const double *accG,
-                                 const double *accU, double *grad_cdd, double *grad_cgd,
+hipError_t launch_soft_bwd_final(const DiagRec *dr, double *accA, double *accG,
+                                 double *accU, double *grad_cdd, double *grad_cgd,
                                  hipStream_t s);
 // charge-sensor response (qa_sensor.hip): the last n_sensor dots of dr are
 // sensors; array charges from n_int or n_dbl (P x (n - n_sensor)); noise

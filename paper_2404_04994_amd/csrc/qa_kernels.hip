@@ -1007,9 +1007,9 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
 }
 
 __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restrict__ dr,
-                                                        const double *__restrict__ accA,
-                                                        const double *__restrict__ accG,
-                                                        const double *__restrict__ accU,
+                                                        double *__restrict__ accA,
+                                                        double *__restrict__ accG,
+                                                        double *__restrict__ accU,
                                                         double *__restrict__ grad_cdd,
                                                         double *__restrict__ grad_cgd)
 {
@@ -1052,6 +1052,11 @@ __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restric
         const int i = e / g, j = e % g;
         grad_cgd[e] = accG[i * kMaxGate + j];
     }
+    // leave the accumulators zero for the next backward pass
+    __syncthreads();
+    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) accA[e] = 0.0;
+    for (int e = tid; e < kMaxDot * kMaxGate; e += blockDim.x) accG[e] = 0.0;
+    for (int e = tid; e < ns; e += blockDim.x) accU[e] = 0.0;
 }
 
 hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P, const double *gbar,
@@ -1071,8 +1076,8 @@ hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P, const 
     return hipGetLastError();
 }
 
-hipError_t launch_soft_bwd_final(const DiagRec *dr, const double *accA, const double *accG,
-                                 const double *accU, double *grad_cdd, double *grad_cgd,
+hipError_t launch_soft_bwd_final(const DiagRec *dr, double *accA, double *accG,
+                                 double *accU, double *grad_cdd, double *grad_cgd,
                                  hipStream_t s)
 {
     hipLaunchKernelGGL(k_soft_bwd_final, dim3(1), dim3(256), 0, s, dr, accA, accG, accU, grad_cdd,

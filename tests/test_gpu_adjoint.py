@@ -48,3 +48,32 @@ def test_adjoint_workload(qa, oracle, npix):
         print("grad %s rel err %.3e" % (name, rel), flush=True)
         assert rel <= 1e-8
     sys.stdout.flush()
+
+
+def test_backward_after_other_diagram_and_repeated(qa):
+    """The backward reuses the forward's prologue when the record still holds
+    it and relies on its accumulators having been left at zero: repeated
+    passes, and a pass after another diagram's forward on the same stream,
+    give the same gradients (to atomic-order rounding)."""
+    case = W.adjoint_case(400, npix=20)
+    other = W.adjoint_case(401, npix=20)
+    Vo = torch.tensor(other.V, dtype=torch.float64, device="cuda")
+
+    def grads(interleave):
+        C = torch.tensor(case.cdd[:8, :8], dtype=torch.float64, requires_grad=True)
+        G = torch.tensor(case.cgd[:8, :], dtype=torch.float64, requires_grad=True)
+        V = torch.tensor(case.V, dtype=torch.float64, device="cuda", requires_grad=True)
+        nbar = qa.soft_charge_autograd(C, G, V, case.kT)
+        if interleave:
+            qa.soft_charge(other.cdd[:8, :8], other.cgd[:8, :], Vo, other.kT)
+        w = torch.linspace(0.5, 1.5, 8, dtype=torch.float64, device="cuda")
+        (nbar @ w).pow(2).sum().backward()
+        torch.cuda.synchronize()
+        return C.grad.numpy().copy(), G.grad.numpy().copy(), V.grad.cpu().numpy().copy()
+
+    ref = grads(False)
+    for interleave in (False, True, False, True):
+        got = grads(interleave)
+        for a, b in zip(got, ref):
+            rel = np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+            assert rel <= 1e-12, (interleave, rel)
