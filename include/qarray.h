@@ -112,13 +112,15 @@ typedef struct {
 
 /* qa_problem.flags.
  *  QA_FLAG_EXHAUSTIVE : the matrix-core scorer computes the energy of every
- *      state of the dense box.  By default the dense box of N >= 13 dots is
- *      searched in bound order: a lower bound of the 256 states that share a
- *      high part (the low part minimised over the reals, whose value is the
- *      Schur complement of the low block of C_dd^{-1}, i.e. the inverse of the
- *      high block of C_dd) discards high parts that cannot hold the argmin or
- *      a state of the near-tie band.  Both give the argmin over the whole box
- *      (Sec. 3.2.1); qa_stats.scored tells how many energies were computed. */
+ *      state of the candidate set.  By default the candidate sets of N >= 13
+ *      dots (the dense box, the thresholded sub-boxes and the closed subsets)
+ *      are searched in bound order: a lower bound of the 256 states that
+ *      share a high part (the low part minimised over the reals, whose value
+ *      is the Schur complement of the low block of C_dd^{-1}, i.e. the inverse
+ *      of the high block of C_dd; closed arrays with the low part's sum fixed)
+ *      discards high parts that cannot hold the argmin or a state of the
+ *      near-tie band.  Both give the argmin over the whole candidate set
+ *      (Sec. 3.2); qa_stats.scored tells how many energies were computed. */
 #define QA_FLAG_EXHAUSTIVE 1
 
 typedef struct {
