@@ -616,7 +616,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         if (PREC == kPrecFP32) {
             bf[ct][0] = (float)((clo >> q) & 1);
             bf[ct][1] = (float)((clo >> (4 + q)) & 1);
-            bf[ct][2] = (q == 0) ? 1.0f : (q == 1 ? h : 0.0f);
+            bf[ct][2] = h;  // h_lo of the lane's column, added with C before the products
         } else {
             if (q < 3) {
 #pragma unroll
@@ -875,7 +875,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         };
         // A operand of tile t: row r of the tile is high index list[16 t + r]
         // (unused rows past cnt get the sentinel constant chunk)
-        auto build_rows = [&](int t, Pack8 &a, float (&af)[3]) {
+        auto build_rows = [&](int t, Pack8 &a, float (&af)[6]) {
             const int idx = t * 16 + mrow;
             const bool real = idx < cnt;
             const int chi = real ? (int)list[idx] : 0;
@@ -886,7 +886,15 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                 const float v1 = (gb + sT1[row][4 + q]) + sT2[rtt][4 + q];
                 af[0] = v0;
                 af[1] = v1;
-                af[2] = (q == 0) ? __uint_as_float(cw.x) : (q == 1 ? 1.0f : 0.0f);
+                // C of the four output rows 4q..4q+3 of this lane: the
+                // accumulator starts at C(row) + h_lo(column), so two
+                // K = 4 products per tile suffice
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int ri = t * 16 + 4 * q + i;
+                    af[2 + i] = ri < cnt ? __uint_as_float(ctab[list[ri]].x) : 1e30f;
+                }
+                (void)cw;
             } else {
                 const float v0 = (ga + sT1[row][2 * q]) + sT2[rtt][2 * q];
                 const float v1 = (gb + sT1[row][2 * q + 1]) + sT2[rtt][2 * q + 1];
@@ -917,12 +925,13 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                 a.u[3] = u23[1];
             }
         };
-        auto tile = [&](const Pack8 &a, const float (&af)[3], int ct) -> f32x4_t {
+        auto tile = [&](const Pack8 &a, const float (&af)[6], int ct) -> f32x4_t {
             f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
             if (PREC == kPrecFP32) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i] = af[2 + i] + bf[ct][2];
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[ct][0], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[ct][1], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[2], bf[ct][2], acc, 0, 0, 0);
             } else {
                 Pack8 b;
                 b.u[0] = bw[ct][0]; b.u[1] = bw[ct][1]; b.u[2] = bw[ct][2]; b.u[3] = bw[ct][3];
@@ -945,7 +954,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         // matrix core
         auto score_tile = [&](int t) {
             Pack8 a;
-            float af[3];
+            float af[6];
             int eq[4];
             build_rows(t, a, af);
             elem_pc(t, eq);
@@ -991,7 +1000,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         int iw;
         {
             Pack8 a;
-            float af[3];
+            float af[6];
             int eq[4];
             build_rows(tw, a, af);
             elem_pc(tw, eq);
@@ -1029,7 +1038,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         uint32_t cbest = 0;
         for (int t = 0; t < ntiles; ++t) {
             Pack8 a;
-            float af[3];
+            float af[6];
             int eq[4];
             build_rows(t, a, af);
             elem_pc(t, eq);
