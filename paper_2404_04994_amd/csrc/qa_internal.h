@@ -217,8 +217,8 @@ hipError_t launch_score_tab(const DiagRec *dr, const PixRec *pr, int64_t P, int3
                             int64_t *counters, int n_dot, hipStream_t s);
 // matrix-core scorer at T = 0; mode 0: the dense box, 1: the sub-box of each
 // pixel's free dots (thresholded), 2: closed arrays (subsets of the free
-// dots with k raised); near ties re-scored in FP64 inside the kernel.  The
-// dense box of N >= 13 dots is searched in bound order unless exhaustive.
+// dots with k raised); near ties re-scored in FP64 inside the kernel.  For
+// N >= 13 dots the candidate sets are searched in bound order unless exhaustive.
 hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int prec, int mode,
                              bool exhaustive, int32_t *n_out, int64_t *counters, int n_dot,
                              hipStream_t s);

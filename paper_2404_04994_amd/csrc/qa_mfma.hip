@@ -530,7 +530,9 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
 }
 
 // ---------------------------------------------------------------------------
-// Bound-ordered search of the dense box (N >= 13: more than one row tile).
+// Bound-ordered search of the candidate sets of N >= 13 dots (more than one
+// row tile): the dense box, the thresholded sub-boxes (MODE kPruned) and the
+// closed subsets (kClosed).
 //
 // The argmin over the 2^N states of the box is found without scoring all of
 // them.  With y = n0 - x_u (so g = A y and U(n0 + b) - U(n0) = b^T g +
@@ -541,16 +543,19 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
 //     s = S y_hi,  K = 1/2 y_hi^T s - U(n0)
 // (the setup forms S in its Gauss-Jordan sweep, the table of
 // 1/2 b_hi^T S b_hi, and s and K of every pixel in FP64).
+// Closed arrays fix the low part's sum at m = k - popc(b_hi), which adds
+// (m - mu - w^T b_hi)^2 / (2 gamma) to the bound.
 // L is a lower bound for all 256 states of a high index, so a high index
-// whose bound lies above the best energy found so far (plus a margin that
-// covers the FP32 error of the bound and three times the certified error
-// band) holds neither the exact argmin nor any state of the near-tie band.
-// Each pixel scores the row tile with the smallest bound first, then only
-// the other high indices whose bound does not exceed the best energy so far
-// plus the margin, sixteen to a tile (a row of the tile is any high index);
-// the rest of the kernel (error band, FP64 re-score of near ties) is that of
-// the dense scorer over the scored rows.  The result is the argmin over the
-// whole box, as in the dense form.
+// whose bound lies above an upper bound of the best approximate energy (plus
+// a margin that covers the FP32 error of the bound and three times the
+// certified error band) holds neither the exact argmin nor any state of the
+// near-tie band.  The upper bound is the energy of the setup's guess (a state
+// of the candidate set) or, when that leaves more than two tiles of rows, the
+// best of the row tile with the smallest bound, scored first.  The rows are
+// scored sixteen to a tile (a row of the tile is any high index); the rest of
+// the kernel (error band, FP64 re-score of near ties) is that of the
+// exhaustive scorer over the scored rows.  The result is the argmin over the
+// whole candidate set, as in the exhaustive form.
 // ---------------------------------------------------------------------------
 template <int PREC, int MODE>
 __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const DiagRec *__restrict__ dr,
