@@ -170,6 +170,31 @@ __device__ __forceinline__ void gj_pivot(double (&r)[NM], double &v, int k, int 
     }
 }
 
+// The same pivot with k fixed at compile time, for 16-lane groups (a DPP
+// row): the pivot row, right-hand side and pivot come by row broadcasts.
+template <int NM, int K>
+__device__ __forceinline__ void gj_pivot_row(double (&r)[NM], double &v, int dot)
+{
+    static_assert(NM == 16, "row broadcasts need 16-lane groups");
+    const double rik = r[K];
+    const double piv = dppd<kDppRowBcast0 + K>(rik);
+    double pr[NM];
+#pragma unroll
+    for (int q = 0; q < NM; ++q) pr[q] = dppd<kDppRowBcast0 + K>(r[q]);
+    const double pv = dppd<kDppRowBcast0 + K>(v);
+    const double rp = 1.0 / piv;
+    if (dot == K) {
+#pragma unroll
+        for (int q = 0; q < NM; ++q) r[q] = pr[q] * rp;
+        v = pv * rp;
+    } else {
+        const double f = rik * rp;
+#pragma unroll
+        for (int q = 0; q < NM; ++q) r[q] -= f * pr[q];
+        v -= f * pv;
+    }
+}
+
 // The block is eight waves: wave 0 inverts C_dd (the diagram prologue, in
 // every block, so that no prologue launch precedes this one) while waves 1-7
 // take 7 * 64 / NM pixels through x_u, the QP and the candidate set, which
@@ -288,8 +313,19 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
                     }
                     v = x0;
                 }
-                for (uint32_t todo = W & ~done; todo; todo &= todo - 1)
-                    gj_pivot<NM>(r, v, __ffs(todo) - 1, dot, base);
+                if constexpr (NM == 16) {
+                    // pivots in increasing dot order (as the shuffle form):
+                    // dot k is pivoted by the groups that need it
+                    const uint32_t todo = W & ~done;
+                    static_for_dev<0, NM>([&](auto kc) {
+                        constexpr int kp = decltype(kc)::value;
+                        if (__ballot(todo >> kp & 1u) && (todo >> kp & 1u))
+                            gj_pivot_row<NM, kp>(r, v, dot);
+                    });
+                } else {
+                    for (uint32_t todo = W & ~done; todo; todo &= todo - 1)
+                        gj_pivot<NM>(r, v, __ffs(todo) - 1, dot, base);
+                }
                 done = W;
                 const bool in_w = W >> dot & 1u;
                 x = in_w ? 0.0 : v;
