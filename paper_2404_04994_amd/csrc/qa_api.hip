@@ -489,26 +489,25 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
     DiagRec *dr0 = w->dr;
     if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
     if (w->dr != dr0) w->dr_inputs.clear();
-    const int64_t nacc = (int64_t)kMaxDot * kMaxDot + (int64_t)kMaxDot * kMaxGate + 4096;
+    const int64_t nacc = (int64_t)kBwdReplicas * kBwdAccWords;
     double *acc0 = w->acc;
     if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
     if (w->acc != acc0) w->acc_zero = false;
     if ((st = upload_diag(w, prob))) return st;
-    double *accA = w->acc, *accG = accA + kMaxDot * kMaxDot, *accU = accG + kMaxDot * kMaxGate;
     // the prologue (A, C_dd 1, tables) only when the record does not already
     // hold it for these inputs (the usual case after the forward call);
     // it also clears the accumulators when they are not known to be zero
     const int64_t nzero = w->acc_zero ? 0 : nacc;
     if (!w->dr_derived) {
-        QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream, nzero ? accA : nullptr, nzero));
+        QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream, nzero ? w->acc : nullptr, nzero));
         w->dr_derived = true;
     } else if (nzero) {
-        QA_HIP(launch_zero_i64(reinterpret_cast<int64_t *>(accA), (int)nzero, w->stream));
+        QA_HIP(launch_zero_i64(reinterpret_cast<int64_t *>(w->acc), (int)nzero, w->stream));
     }
     w->acc_zero = false;  // until the final kernel below is enqueued
-    QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, accA, accG,
-                           accU, grad_V_dev, prob->n_dot, w->stream));
-    QA_HIP(launch_soft_bwd_final(w->dr, accA, accG, accU, grad_cdd_dev, grad_cgd_dev, w->stream));
+    QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, w->acc,
+                           grad_V_dev, prob->n_dot, w->stream));
+    QA_HIP(launch_soft_bwd_final(w->dr, w->acc, grad_cdd_dev, grad_cgd_dev, w->stream));
     w->acc_zero = true;
     return QA_OK;
 }

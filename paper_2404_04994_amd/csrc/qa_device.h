@@ -277,20 +277,49 @@ __device__ __forceinline__ uint64_t free_positions(uint32_t fm)
     return pos;
 }
 
+// All-reductions over aligned groups of 2^LG lanes.  A group of at most 16
+// lanes lies inside one DPP row and takes the first LG of the row steps (each
+// an involution, so every lane ends with the same bits); wider groups use
+// LDS permutes.
 template <int LG>
 __device__ __forceinline__ double group_min(double v)
 {
+    if constexpr (LG <= 4) {
+        if constexpr (LG >= 1) v = fmin(v, dppd<kDppXor1>(v));
+        if constexpr (LG >= 2) v = fmin(v, dppd<kDppXor2>(v));
+        if constexpr (LG >= 3) v = fmin(v, dppd<kDppHalfMirror>(v));
+        if constexpr (LG >= 4) v = fmin(v, dppd<kDppMirror>(v));
+    } else {
 #pragma unroll
-    for (int off = (1 << LG) / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 1 << LG));
+        for (int off = (1 << LG) / 2; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 1 << LG));
+    }
     return v;
 }
 
 template <int LG>
 __device__ __forceinline__ double group_sum(double v)
 {
+    if constexpr (LG <= 4) {
+        if constexpr (LG >= 1) v += dppd<kDppXor1>(v);
+        if constexpr (LG >= 2) v += dppd<kDppXor2>(v);
+        if constexpr (LG >= 3) v += dppd<kDppHalfMirror>(v);
+        if constexpr (LG >= 4) v += dppd<kDppMirror>(v);
+    } else {
 #pragma unroll
-    for (int off = (1 << LG) / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 1 << LG);
+        for (int off = (1 << LG) / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 1 << LG);
+    }
     return v;
+}
+
+// lane Q of each aligned group of 2^LG lanes to the whole group (a DPP row
+// broadcast when the group is one row)
+template <int LG, int Q>
+__device__ __forceinline__ double lane_bcast(double v)
+{
+    if constexpr (LG == 4)
+        return dppd<kDppRowBcast0 + Q>(v);
+    else
+        return __shfl(v, Q, 1 << LG);
 }
 
 // ---------------------------------------------------------------------------

@@ -224,15 +224,17 @@ hipError_t launch_score_mfma(const DiagRec *dr, const PixRec *pr, int64_t P, int
                              hipStream_t s);
 hipError_t launch_soft_fwd(const DiagRec *dr, const PixRec *pr, int64_t P, double *nbar,
                            SavedRec *saved, int64_t *counters, int n_dot, hipStream_t s);
-// adjoint partial sums into accA (kMaxDot^2), accG (kMaxDot x kMaxGate) and
-// accU (2^n), which must be zero on entry
+// adjoint partial sums: kBwdReplicas copies of (dL/dA, kMaxDot^2; dL/dC_gd,
+// kMaxDot x kMaxGate), block b adding into copy b mod kBwdReplicas, so that
+// fewer blocks contend for one address; zero on entry, and left zero by the
+// final kernel, which adds the copies up
+constexpr int kBwdReplicas = 8;
+constexpr int kBwdAccWords = kMaxDot * kMaxDot + kMaxDot * kMaxGate;
 hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P,
-                           const double *gbar, const SavedRec *saved, double *accA,
-                           double *accG, double *accU, double *gradV, int n_dot,
-                           hipStream_t s);
-hipError_t launch_soft_bwd_final(const DiagRec *dr, double *accA, double *accG,
-                                 double *accU, double *grad_cdd, double *grad_cgd,
-                                 hipStream_t s);
+                           const double *gbar, const SavedRec *saved, double *acc,
+                           double *gradV, int n_dot, hipStream_t s);
+hipError_t launch_soft_bwd_final(const DiagRec *dr, double *acc, double *grad_cdd,
+                                 double *grad_cgd, hipStream_t s);
 // charge-sensor response (qa_sensor.hip): the last n_sensor dots of dr are
 // sensors; array charges from n_int or n_dbl (P x (n - n_sensor)); noise
 // draws optional (NULL: none); signal P x n_sensor

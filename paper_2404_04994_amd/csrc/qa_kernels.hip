@@ -715,6 +715,31 @@ __device__ __forceinline__ double tab_energy(const double *__restrict__ sH, cons
     return E;
 }
 
+// The same energies when every free dot is one of the low dots (fm = 2^m - 1,
+// the usual case): candidate q of a lane is s = lane + q 2^LG, so the bits
+// below LG come from the lane (summed once per pixel) and the rest from q,
+// known at compile time once the loop is unrolled.
+template <int LG, int NM, int CPL>
+__device__ __forceinline__ void tab_energies_low(const double *__restrict__ sH,
+                                                 const double (&g0)[NM], double u0,
+                                                 uint32_t count, int k, int lane,
+                                                 double (&e)[CPL])
+{
+    double lo = u0;
+#pragma unroll
+    for (int i = 0; i < LG; ++i)
+        if (lane >> i & 1) lo += g0[i];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        const uint32_t s = (uint32_t)lane + ((uint32_t)q << LG);
+        double L = lo;
+#pragma unroll
+        for (int j = LG; j < NM; ++j)
+            if ((q << LG) >> j & 1) L += g0[j];
+        e[q] = (s < count && (k < 0 || __popc(s) == k)) ? L + sH[s] : INFINITY;
+    }
+}
+
 template <int LG, int NM, int CPL>
 __device__ __forceinline__ void tab_energies(const double *__restrict__ sH, const double (&g0)[NM],
                                              double u0, uint32_t fm, int k, int lane,
@@ -737,7 +762,7 @@ __global__ __launch_bounds__(256) void k_soft_fwd_tab(const DiagRec *__restrict_
     for (int i = threadIdx.x; i < 256; i += blockDim.x) sH[i] = dr->hs[i];
     __syncthreads();
     const int n = dr->n;
-    const double kT = dr->kT;
+    const double ikT = 1.0 / dr->kT;
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
@@ -748,7 +773,12 @@ __global__ __launch_bounds__(256) void k_soft_fwd_tab(const DiagRec *__restrict_
         for (int i = 0; i < NM; ++i) g0[i] = r->g0[i];
         double e[CPL];
         uint32_t st[CPL];
-        tab_energies<LG, NM, CPL>(sH, g0, r->u0, r->free, r->k, lane, e, st);
+        const uint32_t fm = r->free;
+        const bool low = (fm & (fm + 1)) == 0;
+        if (low)
+            tab_energies_low<LG, NM, CPL>(sH, g0, r->u0, 1u << __popc(fm), r->k, lane, e);
+        else
+            tab_energies<LG, NM, CPL>(sH, g0, r->u0, fm, r->k, lane, e, st);
         double lmin = e[0];
 #pragma unroll
         for (int q = 1; q < CPL; ++q) lmin = fmin(lmin, e[q]);
@@ -756,14 +786,30 @@ __global__ __launch_bounds__(256) void k_soft_fwd_tab(const DiagRec *__restrict_
         double z = 0.0, sv[NM];
 #pragma unroll
         for (int i = 0; i < NM; ++i) sv[i] = 0.0;
+        if (low) {
+            // dot i < LG is in every candidate of the lane or in none
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-            if (e[q] < INFINITY) {
-                const double w = exp(-(e[q] - emin) / kT);
-                z += w;
+            for (int q = 0; q < CPL; ++q) {
+                if (e[q] < INFINITY) {
+                    const double w = exp((emin - e[q]) * ikT);
+                    z += w;
 #pragma unroll
-                for (int i = 0; i < NM; ++i)
-                    if (st[q] >> i & 1u) sv[i] += w;
+                    for (int j = LG; j < NM; ++j)
+                        if ((q << LG) >> j & 1) sv[j] += w;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < LG; ++i) sv[i] = (lane >> i & 1) ? z : 0.0;
+        } else {
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                if (e[q] < INFINITY) {
+                    const double w = exp((emin - e[q]) * ikT);
+                    z += w;
+#pragma unroll
+                    for (int i = 0; i < NM; ++i)
+                        if (st[q] >> i & 1u) sv[i] += w;
+                }
             }
         }
         const double Z = group_sum<LG>(z);
@@ -891,15 +937,15 @@ constexpr int kBwdMaxDot = 12;
 // recomputed energies (table form for n <= 8, CPL > 0; the Gray-code walk
 // otherwise).  The per-pixel outer products go to block sums in LDS, spread
 // over the lanes (lane i: row i of the dL/dA sum; lane j: gate column j of
-// the dL/dC_gd sum), and reach HBM once per block.
+// the dL/dC_gd sum); the u_s terms fold into the dL/dA block sum as superset
+// sums, and the block sums reach HBM once per block, as atomic adds into one
+// of kBwdReplicas copies.
 template <int LG, int NM, int CPL>
 __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr,
                                                   const double *__restrict__ V, int64_t P,
                                                   const double *__restrict__ gbar,
                                                   const SavedRec *__restrict__ saved,
-                                                  double *__restrict__ accA,
-                                                  double *__restrict__ accG,
-                                                  double *__restrict__ accU,
+                                                  double *__restrict__ acc,
                                                   double *__restrict__ gradV)
 {
     constexpr int G = 1 << LG;
@@ -922,10 +968,15 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
     for (int i = threadIdx.x; i < NU; i += blockDim.x) sU[i] = 0.0;
     __syncthreads();
     const int n = dr->n, g = dr->g;
-    const double kT = dr->kT;
+    const double ikT = 1.0 / dr->kT;
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
+    // u_s of the lane's own candidates s = lane + q 2^LG (free dots 0..m-1),
+    // summed over the group's pixels and added to the block sum once
+    double uacc[CPL > 0 ? CPL : 1];
+#pragma unroll
+    for (int q = 0; q < (CPL > 0 ? CPL : 1); ++q) uacc[q] = 0.0;
     for (int64_t p = gid; p < P; p += ngroups) {
         // keep the reads of A in LDS inside the loop: hoisted, they would
         // hold N^2 doubles in registers for the whole kernel
@@ -942,9 +993,9 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
         }
         double z[NM], g0[NM], gb[NM];
         double gnb = 0.0;
+        static_for_dev<0, NM>([&](auto I) { z[I] = lane_bcast<LG, I>(zd); });
 #pragma unroll
         for (int i = 0; i < NM; ++i) {
-            z[i] = __shfl(zd, i, G);
             gb[i] = (i < n) ? gbar[p * n + i] : 0.0;
             gnb += gb[i] * sr->nb[i];
         }
@@ -953,11 +1004,9 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
 #pragma unroll
         for (int j = 0; j < NM; ++j) gd += sA[d * kMaxDot + j] * z[j];
         double u0 = 0.0;
+        static_for_dev<0, NM>([&](auto I) { g0[I] = lane_bcast<LG, I>(gd); });
 #pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            g0[i] = __shfl(gd, i, G);
-            u0 += z[i] * g0[i];
-        }
+        for (int i = 0; i < NM; ++i) u0 += z[i] * g0[i];
         u0 *= 0.5;
         const uint32_t fm = sr->free;
         const int k = sr->k;
@@ -966,24 +1015,56 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
         double mv[NM];
 #pragma unroll
         for (int i = 0; i < NM; ++i) mv[i] = 0.0;
+        const double iZ = 1.0 / Z;
         auto add_candidate = [&](uint32_t s, double E) {
-            const double pi = exp(-(E - emin) / kT) / Z;
+            const double pi = exp((emin - E) * ikT) * iZ;
             double gs = 0.0;
 #pragma unroll
             for (int i = 0; i < NM; ++i)
                 if (s >> i & 1u) gs += gb[i];
-            const double ub = -(pi / kT) * (gs - gnb);
+            const double ub = -(pi * ikT) * (gs - gnb);
 #pragma unroll
             for (int i = 0; i < NM; ++i)
                 if (s >> i & 1u) mv[i] += ub;
             atomicAdd(&sU[s], ub);
         };
         if constexpr (CPL > 0) {
+            if ((fm & (fm + 1)) == 0) {
+                // free dots 0..m-1: the same split of s = lane + q 2^LG as
+                // the forward, so dots below LG take the lane's total
+                double e[CPL];
+                tab_energies_low<LG, NM, CPL>(sH, g0, u0, 1u << __popc(fm), k, lane, e);
+                double glo = -gnb;
+#pragma unroll
+                for (int i = 0; i < LG; ++i)
+                    if (lane >> i & 1) glo += gb[i];
+                double tsum = 0.0;
+#pragma unroll
+                for (int q = 0; q < CPL; ++q) {
+                    if (e[q] < INFINITY) {
+                        double gs = glo;
+#pragma unroll
+                        for (int j = LG; j < NM; ++j)
+                            if ((q << LG) >> j & 1) gs += gb[j];
+                        const double ub = -(exp((emin - e[q]) * ikT) * iZ * ikT) * gs;
+                        tsum += ub;
+#pragma unroll
+                        for (int j = LG; j < NM; ++j)
+                            if ((q << LG) >> j & 1) mv[j] += ub;
+                        uacc[q] += ub;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < LG; ++i)
+                    if (lane >> i & 1) mv[i] += tsum;
+            } else {
 #pragma unroll 2
-            for (int q = 0; q < CPL; ++q) {
-                uint32_t sq;
-                const double E = tab_energy<NM>(sH, g0, u0, fm, k, (uint32_t)(lane + (q << LG)), sq);
-                if (E < INFINITY) add_candidate(sq, E);
+                for (int q = 0; q < CPL; ++q) {
+                    uint32_t sq;
+                    const double E =
+                        tab_energy<NM>(sH, g0, u0, fm, k, (uint32_t)(lane + (q << LG)), sq);
+                    if (E < INFINITY) add_candidate(sq, E);
+                }
             }
         }
         const int m = __popc(fm);
@@ -1009,8 +1090,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
 #pragma unroll
         for (int j = 0; j < NM; ++j) dd -= sA[d * kMaxDot + j] * mv[j];
         double dx[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) dx[i] = __shfl(dd, i, G);
+        static_for_dev<0, NM>([&](auto I) { dx[I] = lane_bcast<LG, I>(dd); });
         // lane i < n: row i of 1/2 (z m^T + m z^T)
         double zi = 0.0, mi = 0.0;
 #pragma unroll
@@ -1033,43 +1113,50 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
             if (gradV) gradV[p * g + j] = gv;
         }
     }
+    if constexpr (CPL > 0) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+            if (uacc[q] != 0.0) atomicAdd(&sU[lane + (q << LG)], uacc[q]);
+    }
     __syncthreads();
+    // dL/dA_ij also takes 1/2 sum_s u_s [i in s][j in s] = 1/2 F({i, j}), F the
+    // superset sums of the block's u_s (one dot per pass, in place: a pass
+    // writes only entries without its dot and reads only entries with it)
+    const int nu = 1 << n;
+    for (int b = 0; b < n; ++b) {
+        for (int s = threadIdx.x; s < nu; s += blockDim.x)
+            if (!(s >> b & 1)) sU[s] += sU[s | (1 << b)];
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        sdA[i * kMaxDot + j] += 0.5 * sU[(1 << i) | (1 << j)];
+    }
+    __syncthreads();
+    double *accA = acc + (blockIdx.x & (kBwdReplicas - 1)) * kBwdAccWords;
+    double *accG = accA + kMaxDot * kMaxDot;
     for (int i = threadIdx.x; i < kMaxDot * kMaxDot; i += blockDim.x)
         if (sdA[i] != 0.0) atomicAdd(&accA[i], sdA[i]);
     for (int i = threadIdx.x; i < kMaxDot * kMaxGate; i += blockDim.x)
         if (sdG[i] != 0.0) atomicAdd(&accG[i], sdG[i]);
-    for (int i = threadIdx.x; i < NU; i += blockDim.x)
-        if (sU[i] != 0.0) atomicAdd(&accU[i], sU[i]);
 }
 
 __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restrict__ dr,
-                                                        double *__restrict__ accA,
-                                                        double *__restrict__ accG,
-                                                        double *__restrict__ accU,
+                                                        double *__restrict__ acc,
                                                         double *__restrict__ grad_cdd,
                                                         double *__restrict__ grad_cgd)
 {
-    __shared__ double F[1 << kBwdMaxDot];
     __shared__ double dA[kMaxDot * kMaxDot];
     __shared__ double T[kMaxDot * kMaxDot];
     const int n = dr->n, g = dr->g;
     const int tid = threadIdx.x;
-    const int ns = 1 << n;
-    for (int s = tid; s < ns; s += blockDim.x) F[s] = accU[s];
-    __syncthreads();
-    // superset sums F(T) = sum_{s contains T} u_s, one dot per pass
-    for (int b = 0; b < n; ++b) {
-        for (int s = tid; s < ns; s += blockDim.x)
-            if (!(s >> b & 1)) F[s] += F[s | (1 << b)];
-        __syncthreads();
-    }
-    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) {
-        const int i = e / kMaxDot, j = e % kMaxDot;
-        double v = accA[e];
-        // 1/2 sum_s u_s [i in s][j in s]
-        if (i < n && j < n) v += 0.5 * F[(1 << i) | (1 << j)];
-        dA[e] = v;
-    }
+    auto total = [&](int e) {  // the copies' sum of accumulator word e
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < kBwdReplicas; ++r) v += acc[r * kBwdAccWords + e];
+        return v;
+    };
+    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) dA[e] = total(e);
     __syncthreads();
     for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) {
         const int i = e / kMaxDot, j = e % kMaxDot;
@@ -1086,38 +1173,34 @@ __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restric
     }
     for (int e = tid; e < n * g; e += blockDim.x) {
         const int i = e / g, j = e % g;
-        grad_cgd[e] = accG[i * kMaxGate + j];
+        grad_cgd[e] = total(kMaxDot * kMaxDot + i * kMaxGate + j);
     }
     // leave the accumulators zero for the next backward pass
     __syncthreads();
-    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) accA[e] = 0.0;
-    for (int e = tid; e < kMaxDot * kMaxGate; e += blockDim.x) accG[e] = 0.0;
-    for (int e = tid; e < ns; e += blockDim.x) accU[e] = 0.0;
+    for (int e = tid; e < kBwdReplicas * kBwdAccWords; e += blockDim.x) acc[e] = 0.0;
 }
 
 hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P, const double *gbar,
-                           const SavedRec *saved, double *accA, double *accG, double *accU,
-                           double *gradV, int n_dot, hipStream_t s)
+                           const SavedRec *saved, double *acc, double *gradV, int n_dot,
+                           hipStream_t s)
 {
-    // accA, accG, accU: zeroed by the caller's prologue launch
+    // acc: zeroed by the caller's prologue launch or left zero by the last
+    // final kernel
     if (n_dot <= 8) {
         QA_DISPATCH_TAB(n_dot, hipLaunchKernelGGL((k_soft_bwd<LG_, NM_, CPL_>),
                                                   dim3(group_blocks(P, LG_, 2048)), dim3(256), 0,
-                                                  s, dr, V, P, gbar, saved, accA, accG, accU,
-                                                  gradV));
+                                                  s, dr, V, P, gbar, saved, acc, gradV));
     } else {
         hipLaunchKernelGGL((k_soft_bwd<6, 16, 0>), dim3(group_blocks(P, 6, 2048)), dim3(256), 0,
-                           s, dr, V, P, gbar, saved, accA, accG, accU, gradV);
+                           s, dr, V, P, gbar, saved, acc, gradV);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_soft_bwd_final(const DiagRec *dr, double *accA, double *accG,
-                                 double *accU, double *grad_cdd, double *grad_cgd,
-                                 hipStream_t s)
+hipError_t launch_soft_bwd_final(const DiagRec *dr, double *acc, double *grad_cdd,
+                                 double *grad_cgd, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_soft_bwd_final, dim3(1), dim3(256), 0, s, dr, accA, accG, accU, grad_cdd,
-                       grad_cgd);
+    hipLaunchKernelGGL(k_soft_bwd_final, dim3(1), dim3(256), 0, s, dr, acc, grad_cdd, grad_cgd);
     return hipGetLastError();
 }
 

@@ -226,6 +226,35 @@ def test_soft_backward_matches_oracle(qa, oracle, closed):
         assert rel <= 1e-9
 
 
+@pytest.mark.parametrize("n,closed", [(6, False), (6, True), (10, False), (10, True)])
+def test_soft_backward_fixed_dots_and_walk_form(qa, oracle, n, closed):
+    """Chains of 6 (candidate table) and 10 dots (Gray-code walk) with the
+    thresholded candidate sets of Sec. 3.2.2 (t = 0.5), so that free masks
+    with gaps occur beside masks of low dots only; 40 pixels."""
+    rng = np.random.default_rng(300 + n + 7 * closed)
+    cdd = np.diag(rng.uniform(1.0, 1.4, n))
+    for i in range(n - 1):
+        cdd[i, i + 1] = cdd[i + 1, i] = -rng.uniform(0.1, 0.3)
+    cgd = np.diag(rng.uniform(0.5, 1.0, n))
+    V = rng.uniform(-1, 3, (40, n))
+    kT, nhat, t = 0.05, n // 2, 0.5
+    Gb = rng.standard_normal((V.shape[0], n))
+    st = oracle.method_setup(cdd, cgd, V, closed=closed, nhat=nhat, t=t)
+    masks = st["freemask"].astype(np.int64)
+    say("masks with gaps", int(((masks & (masks + 1)) != 0).sum()), "of", len(masks))
+    assert ((masks & (masks + 1)) != 0).any() and ((masks & (masks + 1)) == 0).any()
+    rC, rG, rV = oracle.soft_grad(cdd, cgd, V, kT, st["n0"], st["freemask"], st["k"], Gb)
+    Vt = torch.as_tensor(V).cuda()
+    nbar, saved = qa.soft_charge(cdd, cgd, Vt, kT, closed, nhat, t)
+    dC, dG, dV = qa.soft_charge_backward(cdd, cgd, Vt, kT, torch.as_tensor(Gb).cuda(), saved,
+                                         closed, nhat, t)
+    for a, b, name in ((dC, rC, "C_dd"), (dG, rG, "C_gd"), (dV, rV, "V")):
+        a = a.cpu().numpy()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+        say("grad", name, "rel err %.3e" % rel)
+        assert rel <= 1e-9
+
+
 @pytest.mark.parametrize("t", [2 / 3, 0.5, 1 / 3])
 def test_grid16_thresholded(qa, oracle, t):
     """The 16-dot array with the thresholded candidate sets of Sec. 3.2.2."""
