@@ -940,8 +940,10 @@ constexpr int kBwdMaxDot = 12;
 // the dL/dC_gd sum); the u_s terms fold into the dL/dA block sum as superset
 // sums, and the block sums reach HBM once per block, as atomic adds into one
 // of kBwdReplicas copies.
+// The table form is held to 168 VGPRs (three waves per SIMD, so that a
+// 10^4-pixel launch is resident at once); the walk form would spill there.
 template <int LG, int NM, int CPL>
-__global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CPL > 0 ? 3 : 1))) void k_soft_bwd(const DiagRec *__restrict__ dr,
                                                   const double *__restrict__ V, int64_t P,
                                                   const double *__restrict__ gbar,
                                                   const SavedRec *__restrict__ saved,
@@ -972,11 +974,6 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
-    // u_s of the lane's own candidates s = lane + q 2^LG (free dots 0..m-1),
-    // summed over the group's pixels and added to the block sum once
-    double uacc[CPL > 0 ? CPL : 1];
-#pragma unroll
-    for (int q = 0; q < (CPL > 0 ? CPL : 1); ++q) uacc[q] = 0.0;
     for (int64_t p = gid; p < P; p += ngroups) {
         // keep the reads of A in LDS inside the loop: hoisted, they would
         // hold N^2 doubles in registers for the whole kernel
@@ -1051,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
 #pragma unroll
                         for (int j = LG; j < NM; ++j)
                             if ((q << LG) >> j & 1) mv[j] += ub;
-                        uacc[q] += ub;
+                        atomicAdd(&sU[lane + (q << LG)], ub);
                     }
                 }
 #pragma unroll
@@ -1113,11 +1110,6 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const DiagRec *__restrict__ dr
             if (gradV) gradV[p * g + j] = gv;
         }
     }
-    if constexpr (CPL > 0) {
-#pragma unroll
-        for (int q = 0; q < CPL; ++q)
-            if (uacc[q] != 0.0) atomicAdd(&sU[lane + (q << LG)], uacc[q]);
-    }
     __syncthreads();
     // dL/dA_ij also takes 1/2 sum_s u_s [i in s][j in s] = 1/2 F({i, j}), F the
     // superset sums of the block's u_s (one dot per pass, in place: a pass
@@ -1146,8 +1138,10 @@ __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restric
                                                         double *__restrict__ grad_cdd,
                                                         double *__restrict__ grad_cgd)
 {
+    __shared__ double sA[kMaxDot * kMaxDot];
     __shared__ double dA[kMaxDot * kMaxDot];
     __shared__ double T[kMaxDot * kMaxDot];
+    __shared__ double dG[kMaxDot * kMaxGate];
     const int n = dr->n, g = dr->g;
     const int tid = threadIdx.x;
     auto total = [&](int e) {  // the copies' sum of accumulator word e
@@ -1156,28 +1150,32 @@ __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restric
         for (int r = 0; r < kBwdReplicas; ++r) v += acc[r * kBwdAccWords + e];
         return v;
     };
-    for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) dA[e] = total(e);
-    __syncthreads();
+    // every global read up front, in one round trip
     for (int e = tid; e < kMaxDot * kMaxDot; e += blockDim.x) {
-        const int i = e / kMaxDot, j = e % kMaxDot;
-        double v = 0.0;
-        for (int a = 0; a < n; ++a) v += dA[i * kMaxDot + a] * dr->A[a * kMaxDot + j];
-        T[e] = v;  // (dL/dA) A
+        sA[e] = dr->A[e];
+        dA[e] = total(e);
     }
+    for (int e = tid; e < n * g; e += blockDim.x) {
+        const int i = e / g, j = e % g;
+        dG[e] = total(kMaxDot * kMaxDot + i * kMaxGate + j);
+    }
+    __syncthreads();
+    // leave the accumulators zero for the next backward pass
+    for (int e = tid; e < kBwdReplicas * kBwdAccWords; e += blockDim.x) acc[e] = 0.0;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e % n;
+        double v = 0.0;
+        for (int a = 0; a < n; ++a) v += dA[i * kMaxDot + a] * sA[a * kMaxDot + j];
+        T[i * kMaxDot + j] = v;  // (dL/dA) A
+    }
+    for (int e = tid; e < n * g; e += blockDim.x) grad_cgd[e] = dG[e];
     __syncthreads();
     for (int e = tid; e < n * n; e += blockDim.x) {
         const int i = e / n, j = e % n;
         double v = 0.0;
-        for (int a = 0; a < n; ++a) v += dr->A[i * kMaxDot + a] * T[a * kMaxDot + j];
+        for (int a = 0; a < n; ++a) v += sA[i * kMaxDot + a] * T[a * kMaxDot + j];
         grad_cdd[e] = -v;
     }
-    for (int e = tid; e < n * g; e += blockDim.x) {
-        const int i = e / g, j = e % g;
-        grad_cgd[e] = total(kMaxDot * kMaxDot + i * kMaxGate + j);
-    }
-    // leave the accumulators zero for the next backward pass
-    __syncthreads();
-    for (int e = tid; e < kBwdReplicas * kBwdAccWords; e += blockDim.x) acc[e] = 0.0;
 }
 
 hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P, const double *gbar,
