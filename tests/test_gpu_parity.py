@@ -185,6 +185,31 @@ def test_soft_closed_and_thresholded(qa, oracle):
     check_soft(qa, oracle, d.cdd, d.cgd, d.V, 0.02, closed=True, nhat=2, t=0.3)
 
 
+@pytest.mark.parametrize("n", [1, 3, 5])
+def test_soft_small_groups(qa, oracle, n):
+    """1, 3 and 5 dots: lane groups of 2, 8 and 16 lanes (the first one,
+    three and four steps of the row reductions), forward and adjoint."""
+    rng = np.random.default_rng(900 + n)
+    cdd = np.diag(rng.uniform(1.0, 1.4, n))
+    for i in range(n - 1):
+        cdd[i, i + 1] = cdd[i + 1, i] = -rng.uniform(0.1, 0.3)
+    cgd = np.diag(rng.uniform(0.5, 1.0, n))
+    V = rng.uniform(-1, 3, (70, n))
+    kT = 0.05
+    check_soft(qa, oracle, cdd, cgd, V, kT)
+    Gb = rng.standard_normal((V.shape[0], n))
+    st = oracle.method_setup(cdd, cgd, V)
+    rC, rG, rV = oracle.soft_grad(cdd, cgd, V, kT, st["n0"], st["freemask"], st["k"], Gb)
+    Vt = torch.as_tensor(V).cuda()
+    nbar, saved = qa.soft_charge(cdd, cgd, Vt, kT)
+    dC, dG, dV = qa.soft_charge_backward(cdd, cgd, Vt, kT, torch.as_tensor(Gb).cuda(), saved)
+    for a, b, name in ((dC, rC, "C_dd"), (dG, rG, "C_gd"), (dV, rV, "V")):
+        a = a.cpu().numpy()
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+        say("grad", name, "rel err %.3e" % rel)
+        assert rel <= 1e-9
+
+
 def test_soft_double_dot_and_8dot(qa, oracle):
     d = W.double_dot(3, npix=60)
     check_soft(qa, oracle, d.cdd, d.cgd, d.V, 0.01)
