@@ -266,36 +266,43 @@ def paper_example():
                    meta=dict(workload="worked example of Sec. 5"))
 
 
-def random_maxwell(n_dot: int, seed: int, n_gate: int | None = None):
+def random_maxwell(n_dot: int, seed: int, n_gate: int | None = None, dot_scale: float = 1.0):
     """Random capacitances as in the paper's benchmark (Sec. 7): every element
-    of the full dot+gate capacitance matrix drawn uniformly, then converted to
-    the Maxwell form (App. B, diagonal = row sum, off-diagonal = minus the
-    element).  Returns (cdd, cgd) with cgd taken positive (coupling)."""
+    of the (N + G) x (N + G) capacitance matrix between the nodes (dots, then
+    gates) drawn from U[0, 1), symmetric (the upper triangle, diagonal
+    included, is drawn and mirrored; a diagonal element is the node's
+    capacitance to ground), then converted to the Maxwell form of App. B:
+    diagonal = the sum of the node's row, off-diagonal = minus the element.
+    Returns (cdd, cgd) with cgd taken positive (coupling).
+
+    ``dot_scale`` multiplies the dot-dot elements before the conversion;
+    1 is the paper's draw.  Values below 1 give a weakly coupled variant that
+    is not the paper's benchmark."""
     rng = np.random.default_rng(seed)
     n_gate = n_dot if n_gate is None else n_gate
     m = n_dot + n_gate
-    c = rng.uniform(0.0, 1.0, (m, m))
-    c = 0.5 * (c + c.T)
-    np.fill_diagonal(c, 0.0)
-    # weak dot-dot coupling relative to the gates keeps the model in the regime
-    # the paper describes (weakly coupled dots, App. F)
-    c[:n_dot, :n_dot] *= 0.2
-    maxwell = np.diag(c.sum(axis=1)) - c
+    c = np.triu(rng.uniform(0.0, 1.0, (m, m)))
+    c = c + np.triu(c, 1).T
+    off = c - np.diag(np.diag(c))
+    off[:n_dot, :n_dot] *= dot_scale
+    maxwell = np.diag(off.sum(axis=1) + np.diag(c)) - off
     cdd = maxwell[:n_dot, :n_dot].copy()
     cgd = -maxwell[:n_dot, n_dot:].copy()
     return cdd, cgd
 
 
 def paper_replica(n_dot: int, seed: int = 500, npix: int = 100, closed: bool = False,
-                  vmin: float = -1.0, vmax: float = 2.0) -> Diagram:
+                  vmin: float = -1.0, vmax: float = 2.0, dot_scale: float = 1.0) -> Diagram:
     """The paper's benchmark (Sec. 7): random capacitances (``random_maxwell``,
     one gate per dot) and npix x npix gate-voltage configurations drawn
     uniformly in [vmin, vmax]^G (the paper gives no range; negative voltages
     make some analytic minima infeasible, so the QP runs too); closed arrays
-    hold as many carriers as dots."""
-    cdd, cgd = random_maxwell(n_dot, seed)
+    hold as many carriers as dots.  ``dot_scale`` < 1 is the weakly coupled
+    variant (not the paper's draw)."""
+    cdd, cgd = random_maxwell(n_dot, seed, dot_scale=dot_scale)
     rng = np.random.default_rng(seed + 7)
     V = rng.uniform(vmin, vmax, (npix * npix, cgd.shape[1]))
     return Diagram(cdd, cgd, V, closed=closed, nhat=n_dot if closed else 0,
-                   meta=dict(workload="paper benchmark replica", seed=seed))
-
+                   meta=dict(workload="paper benchmark replica" if dot_scale == 1.0 else
+                             "paper benchmark replica, dot-dot couplings x %g" % dot_scale,
+                             seed=seed))
