@@ -142,6 +142,25 @@ typedef struct {
 qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P,
                           int32_t *n_out_dev, qa_stats *stats, void *hip_stream);
 
+/* qa_ground_state for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same problem, inputs, output and result as qa_ground_state,
+ * but the call allocates nothing (no hipMalloc, hipHostMalloc or hipFree,
+ * no host heap) and issues no copy: the problem's inputs travel as kernel
+ * arguments, and every intermediate (diagram record, per-pixel records,
+ * counters) lives in a static device array of about 15 MB that each GPU the
+ * library runs on holds until the process ends.
+ *   P : 0..QA_NOALLOC_MAX_PIXELS; larger P returns QA_E_SHAPE (nothing is
+ *       enqueued).  Split larger sweeps into several calls.
+ * No statistics and no stage timing.  Every call on one GPU uses that GPU's
+ * one scratch array and leaves the last call's contents in it: calls that
+ * overlap on one GPU (different streams, or different threads without
+ * ordering) race and give wrong results, so order them on one stream.
+ * The call enqueues on hip_stream and returns without waiting. */
+#define QA_NOALLOC_MAX_PIXELS 65536
+qa_status qa_ground_state_noalloc(const qa_problem *prob, const double *V_dev, int64_t P,
+                                  int32_t *n_out_dev, void *hip_stream);
+
 /* Constrained continuous minimum of every pixel (Sec. 3.1): x* = the
  * analytic minimum (Sec. 3.1.1; App. C for open, App. D for closed arrays)
  * when it is non-negative, otherwise the exact solution of the QP of

@@ -21,16 +21,20 @@ using namespace qa;
 
 namespace {
 
-thread_local std::string g_err;
+// message of the last failure on this thread (a fixed buffer: recording an
+// error allocates nothing)
+thread_local char g_err[512];
+
+void clear_error() { g_err[0] = '\0'; }
 
 qa_status fail(qa_status s, const char *fmt, ...)
 {
-    char buf[512];
+    char buf[sizeof g_err];
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_err = buf;
+    std::memcpy(g_err, buf, sizeof g_err);
     return s;
 }
 
@@ -294,35 +298,43 @@ int scorer_mode(const qa_problem *pb)
     return pb->mode == QA_CLOSED ? 2 : (pb->threshold < 1.0 ? 1 : 0);
 }
 
-// The device work of one single-diagram call on stream s (inputs already in
-// w->dr): prologue, setup and QP in one kernel, then either the T = 0
-// scoring (n_out) or the softargmin (nbar, saved).  ev: optional stage events.
+// The device work of one single-diagram call on stream s, with the inputs
+// already in dr: prologue, setup and QP in one kernel, then either the T = 0
+// scoring (n_out) or the softargmin (nbar, saved).  pr holds P pixel records,
+// bstats 4 * setup_blocks(P, n_dot) counts.  ev: optional stage events.
+qa_status enqueue_path(DiagRec *dr, PixRec *pr, int64_t *counters, int32_t *bstats, hipStream_t s,
+                       const qa_problem *pb, const double *V, int64_t P, int32_t *n_out,
+                       double *nbar, SavedRec *saved, std::array<hipEvent_t, 4> *ev)
+{
+    const bool closed = pb->mode == QA_CLOSED;
+    if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
+    QA_HIP(launch_setup(dr, V, P, pr, counters, bstats, pb->n_dot, closed, s));
+    if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
+    if (nbar) {
+        QA_HIP(launch_soft_fwd(dr, pr, P, nbar, saved, counters, pb->n_dot, s));
+    } else if (use_matrix_cores(pb)) {
+        QA_HIP(launch_score_mfma(dr, pr, P, pb->precision, scorer_mode(pb),
+                                 (pb->flags & QA_FLAG_EXHAUSTIVE) != 0, n_out, counters,
+                                 pb->n_dot, s));
+    } else if (pb->n_dot <= 8) {
+        QA_HIP(launch_score_tab(dr, pr, P, n_out, counters, pb->n_dot, s));
+    } else {
+        QA_HIP(launch_score_fp64(dr, pr, P, n_out, counters, pb->n_dot, s));
+    }
+    if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
+    if (ev) QA_HIP(hipEventRecord((*ev)[3], s));
+    return QA_OK;
+}
+
+// the same on a workspace's buffers
 qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, const double *V,
                          int64_t P, int32_t *n_out, double *nbar, SavedRec *saved,
                          std::array<hipEvent_t, 4> *ev)
 {
-    const bool closed = pb->mode == QA_CLOSED;
-    if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
-    QA_HIP(launch_setup(w->dr, V, P, w->pr, w->counters, w->bstats, pb->n_dot, closed, s));
-    w->dr_derived = true;
-    if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
-    if (nbar) {
-        QA_HIP(launch_soft_fwd(w->dr, w->pr, P, nbar, saved, w->counters, pb->n_dot, s));
-        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
-    } else if (use_matrix_cores(pb)) {
-        QA_HIP(launch_score_mfma(w->dr, w->pr, P, pb->precision, scorer_mode(pb),
-                                 (pb->flags & QA_FLAG_EXHAUSTIVE) != 0, n_out, w->counters,
-                                 pb->n_dot, s));
-        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
-    } else if (pb->n_dot <= 8) {
-        QA_HIP(launch_score_tab(w->dr, w->pr, P, n_out, w->counters, pb->n_dot, s));
-        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
-    } else {
-        QA_HIP(launch_score_fp64(w->dr, w->pr, P, n_out, w->counters, pb->n_dot, s));
-        if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
-    }
-    if (ev) QA_HIP(hipEventRecord((*ev)[3], s));
-    return QA_OK;
+    qa_status st = enqueue_path(w->dr, w->pr, w->counters, w->bstats, s, pb, V, P, n_out, nbar,
+                                saved, ev);
+    if (!st) w->dr_derived = true;
+    return st;
 }
 
 // Run a single-diagram call: with stage timing on, direct launches with
@@ -402,12 +414,92 @@ qa_status read_stats(Workspace *w, qa_stats *stats)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Library-owned device scratch of qa_ground_state_noalloc: the diagram
+// record, the counters, the setup kernel's per-block counts and one record
+// per pixel, for at most QA_NOALLOC_MAX_PIXELS pixels.  Every device the
+// library runs on holds its own copy for the life of the process.  In host
+// code `scratch` names a host-side stand-in: kernels get the device address
+// that hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kScrDiag = 0;
+constexpr size_t kScrCounters = kScrDiag + align256(sizeof(DiagRec));
+constexpr size_t kScrBstats = kScrCounters + align256(sizeof(int64_t) * kCounterWords);
+constexpr int64_t kScrBstatsWords = 4 * setup_blocks_max(QA_NOALLOC_MAX_PIXELS);
+constexpr size_t kScrPix = kScrBstats + align256(sizeof(int32_t) * kScrBstatsWords);
+constexpr size_t kScratchBytes = kScrPix + sizeof(PixRec) * (size_t)QA_NOALLOC_MAX_PIXELS;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kMaxDevices] = {};
+
+// device address of the current device's scratch, looked up once per device
+qa_status scratch_address(unsigned char **out)
+{
+    int dev = 0;
+    QA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(QA_E_DEVICE, "device %d beyond the %d this build tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(QA_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return QA_OK;
+}
+
+// a diagram's inputs into dr as kernel arguments: the header and C_dd in one
+// chunk, C_gd in chunks of whole rows (at most two for n_gate <= 32)
+qa_status put_inputs(DiagRec *dr, const qa_problem *pb, hipStream_t s)
+{
+    InputChunk c;
+    std::memset(&c, 0, sizeof c);
+    const int n = pb->n_dot, g = pb->n_gate;
+    c.n = n;
+    c.g = g;
+    c.closed = pb->mode == QA_CLOSED;
+    c.nhat = pb->mode == QA_CLOSED ? pb->n_charge : 0;
+    c.kT = pb->kT;
+    c.t = pb->threshold;
+    c.prec = pb->precision;
+    c.part = 0;
+    std::memcpy(c.v, pb->cdd, sizeof(double) * n * n);
+    QA_HIP(launch_put_inputs(dr, c, s));
+    c.part = 1;
+    const int rows_per_chunk = kChunkDoubles / g;
+    for (int r0 = 0; r0 < kMaxDot; r0 += rows_per_chunk) {
+        const int r1 = std::min(r0 + rows_per_chunk, n);
+        c.row0 = r0;
+        // the last chunk also writes the zero rows past n
+        c.row1 = r1 >= n ? kMaxDot : r1;
+        std::memset(c.v, 0, sizeof c.v);
+        if (r1 > r0) std::memcpy(c.v, pb->cgd + (size_t)r0 * g, sizeof(double) * (r1 - r0) * g);
+        QA_HIP(launch_put_inputs(dr, c, s));
+        if (c.row1 == kMaxDot) break;
+    }
+    return QA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P,
                           int32_t *n_out_dev, qa_stats *stats, void *hip_stream)
 {
-    g_err.clear();
+    clear_error();
     qa_status st = validate(prob, false);
     if (st) return st;
     if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
@@ -422,11 +514,37 @@ qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P
     return read_stats(w, stats);
 }
 
+qa_status qa_ground_state_noalloc(const qa_problem *prob, const double *V_dev, int64_t P,
+                                  int32_t *n_out_dev, void *hip_stream)
+{
+    clear_error();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    if (P < 0 || P > QA_NOALLOC_MAX_PIXELS)
+        return fail(QA_E_SHAPE, "P=%lld outside [0, %d], the pixels the static scratch holds",
+                    (long long)P, QA_NOALLOC_MAX_PIXELS);
+    if (P == 0) return QA_OK;
+    if (!V_dev || !n_out_dev) return fail(QA_E_NULL, "V_dev or n_out_dev is NULL");
+    if (4 * setup_blocks(P, prob->n_dot) > kScrBstatsWords)
+        return fail(QA_E_SHAPE, "P=%lld needs more setup blocks than the scratch counts",
+                    (long long)P);
+    unsigned char *base;
+    if ((st = scratch_address(&base))) return st;
+    DiagRec *dr = reinterpret_cast<DiagRec *>(base + kScrDiag);
+    int64_t *counters = reinterpret_cast<int64_t *>(base + kScrCounters);
+    int32_t *bstats = reinterpret_cast<int32_t *>(base + kScrBstats);
+    PixRec *pr = reinterpret_cast<PixRec *>(base + kScrPix);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if ((st = put_inputs(dr, prob, s))) return st;
+    return enqueue_path(dr, pr, counters, bstats, s, prob, V_dev, P, n_out_dev, nullptr, nullptr,
+                        nullptr);
+}
+
 qa_status qa_continuous_min(const qa_problem *prob, const double *V_dev, int64_t P,
                             double *x_out_dev, int32_t *flags_out_dev, qa_stats *stats,
                             void *hip_stream)
 {
-    g_err.clear();
+    clear_error();
     qa_status st = validate(prob, false);
     if (st) return st;
     if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
@@ -454,7 +572,7 @@ size_t qa_saved_bytes(int64_t P, int32_t n_dot)
 qa_status qa_soft_charge(const qa_problem *prob, const double *V_dev, int64_t P,
                          double *nbar_out_dev, void *saved_dev, qa_stats *stats, void *hip_stream)
 {
-    g_err.clear();
+    clear_error();
     qa_status st = validate(prob, true);
     if (st) return st;
     if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
@@ -475,7 +593,7 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
                                   double *grad_cdd_dev, double *grad_cgd_dev, double *grad_V_dev,
                                   void *hip_stream)
 {
-    g_err.clear();
+    clear_error();
     qa_status st = validate(prob, true);
     if (st) return st;
     if (prob->n_dot > 12)
@@ -627,7 +745,7 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
                                   const int64_t *out_offsets, int32_t *n_out_dev,
                                   double *nbar_out_dev, qa_stats *stats, void *hip_stream)
 {
-    g_err.clear();
+    clear_error();
     read_env();
     if (n_diag < 0) return fail(QA_E_SHAPE, "n_diag=%d is negative", n_diag);
     if (n_diag == 0) {
@@ -639,7 +757,7 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
     int64_t total = 0;
     for (int d = 0; d < n_diag; ++d) {
         qa_status st = validate(&probs[d], false);
-        if (st) return fail(st, "diagram %d: %s", d, g_err.c_str());
+        if (st) return fail(st, "diagram %d: %s", d, g_err);
         if (pix_counts[d] < 0 || v_offsets[d] < 0 || out_offsets[d] < 0)
             return fail(QA_E_SHAPE, "diagram %d: negative pixel count or offset", d);
         total += pix_counts[d];
@@ -754,7 +872,7 @@ void qa_timing_reset(void *hip_stream)
 
 qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out)
 {
-    g_err.clear();
+    clear_error();
     if (!ms_out) return fail(QA_E_NULL, "ms_out is NULL");
     Workspace *w;
     qa_status st;
@@ -773,7 +891,7 @@ qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out)
     return QA_OK;
 }
 
-const char *qa_last_error(void) { return g_err.c_str(); }
+const char *qa_last_error(void) { return g_err; }
 
 void qa_release(void *hip_stream)
 {
@@ -824,7 +942,7 @@ qa_status qa_sensor_response(const qa_problem *prob, const qa_sensor *sp, const 
                              int64_t P, const int32_t *n_array_dev, const double *nbar_array_dev,
                              const double *noise_dev, double *signal_dev, void *hip_stream)
 {
-    g_err.clear();
+    clear_error();
     qa_status st = validate(prob, false);
     if (st) return st;
     if (!sp) return fail(QA_E_NULL, "sensor parameters are NULL");
@@ -984,7 +1102,7 @@ extern "C" {
 
 qa_status qa_optimal_gate_voltages(const qa_problem *prob, const double *q, double *v_out)
 {
-    g_err.clear();
+    clear_error();
     qa_status st = validate(prob, false);
     if (st) return st;
     if (!q || !v_out) return fail(QA_E_NULL, "q or v_out is NULL");
@@ -1016,7 +1134,7 @@ qa_status qa_optimal_gate_voltages(const qa_problem *prob, const double *q, doub
 
 qa_status qa_virtual_gate_matrix(const qa_problem *prob, double *alpha_out)
 {
-    g_err.clear();
+    clear_error();
     qa_status st = validate(prob, false);
     if (st) return st;
     if (!alpha_out) return fail(QA_E_NULL, "alpha_out is NULL");

@@ -191,11 +191,36 @@ struct alignas(8) BatchHdr {
     int64_t tile0;    // first 64-pixel work item of the diagram
 };
 
+// The inputs of a DiagRec carried in a kernel's arguments (no host staging
+// buffer and no copy call): part 0 writes the header and C_dd, part 1 rows
+// [row0, row1) of C_gd; entries past the problem's n x n and n x g are
+// written as zeros, so the record's padding is the same whatever an earlier
+// call left there.  A chunk holds at most kChunkDoubles matrix entries.
+constexpr int kChunkDoubles = 256;
+struct InputChunk {
+    int32_t n, g, closed, nhat;
+    double kT, t;
+    int32_t prec;
+    int32_t part;        // 0: header and C_dd; 1: C_gd rows [row0, row1)
+    int32_t row0, row1;  // part 1: rows of the padded C_gd written by this chunk
+    double v[kChunkDoubles];  // part 0: C_dd, n x n; part 1: rows row0.. of C_gd, each g long
+};
+
+// the setup kernel: one wave for the prologue, seven for the pixels
+constexpr int kSetupPixThreads = 7 * kWave;
+// its grid is largest for 16-lane pixel groups
+constexpr int64_t setup_blocks_max(int64_t P)
+{
+    return P < 1 ? 1 : (P * kMaxDot + kSetupPixThreads - 1) / kSetupPixThreads;
+}
+
 // -------------------------------------------------------------------------
 // launch wrappers (qa_kernels.hip); all enqueue on `s` and return the HIP
 // error of the launch.
 // -------------------------------------------------------------------------
 hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s);
+// one chunk of a diagram's inputs into dr
+hipError_t launch_put_inputs(DiagRec *dr, const InputChunk &c, hipStream_t s);
 // prologue of n_diag diagrams; also zeroes the kCounterWords counters and
 // the nzero doubles at zero when given
 hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s,

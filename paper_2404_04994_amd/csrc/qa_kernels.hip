@@ -30,6 +30,38 @@ hipError_t launch_zero_i64(int64_t *p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_put_inputs(DiagRec *__restrict__ dr, const InputChunk c)
+{
+    if (c.part == 0) {
+        if (threadIdx.x == 0) {
+            dr->n = c.n;
+            dr->g = c.g;
+            dr->closed = c.closed;
+            dr->nhat = c.nhat;
+            dr->kT = c.kT;
+            dr->t = c.t;
+            dr->prec = c.prec;
+            dr->pad0 = 0;
+        }
+        for (int e = threadIdx.x; e < kMaxDot * kMaxDot; e += blockDim.x) {
+            const int i = e / kMaxDot, j = e % kMaxDot;
+            dr->Cdd[e] = (i < c.n && j < c.n) ? c.v[i * c.n + j] : 0.0;
+        }
+    } else {
+        const int rows = c.row1 - c.row0;
+        for (int e = threadIdx.x; e < rows * kMaxGate; e += blockDim.x) {
+            const int i = e / kMaxGate, j = e % kMaxGate, r = c.row0 + i;
+            dr->Cgd[r * kMaxGate + j] = (r < c.n && j < c.g) ? c.v[i * c.g + j] : 0.0;
+        }
+    }
+}
+
+hipError_t launch_put_inputs(DiagRec *dr, const InputChunk &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_put_inputs, dim3(1), dim3(256), 0, s, dr, c);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // K0: per-diagram prologue, one 256-thread block per diagram
 // ---------------------------------------------------------------------------
@@ -202,7 +234,6 @@ __device__ __forceinline__ void gj_pivot_row(double (&r)[NM], double &v, int dot
 // for the base-state gradient.  (Eight waves: two blocks fill a CU at four
 // waves per SIMD; five-wave blocks left a fifth of the grid waiting for a
 // second round.)
-constexpr int kSetupPixThreads = 7 * kWave;
 constexpr int kSetupThreads = kWave + kSetupPixThreads;
 
 template <int NM, bool CLOSED>

@@ -20,7 +20,7 @@ QA_OPEN, QA_CLOSED = 0, 1
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
 STATUS = {0: "QA_OK", 1: "QA_E_NULL", 2: "QA_E_SHAPE", 3: "QA_E_NOT_SYMMETRIC", 4: "QA_E_NOT_PD",
           5: "QA_E_RANGE", 6: "QA_E_UNSUPPORTED", 7: "QA_E_WORKSPACE", 8: "QA_E_DEVICE"}
-EXPORTS = ("qa_ground_state", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
+EXPORTS = ("qa_ground_state", "qa_ground_state_noalloc", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
            "qa_ground_state_batched", "qa_last_error", "qa_release", "qa_version",
            "qa_timing_enable", "qa_timing_reset", "qa_timing_sum", "qa_graphs_enable")
 
@@ -64,6 +64,7 @@ def load():
         vp, pb, st = C.c_void_p, C.POINTER(Problem), C.POINTER(Stats)
         i64p = C.POINTER(C.c_int64)
         lib.qa_ground_state.argtypes = [pb, vp, C.c_int64, vp, st, vp]
+        lib.qa_ground_state_noalloc.argtypes = [pb, vp, C.c_int64, vp, vp]
         lib.qa_soft_charge.argtypes = [pb, vp, C.c_int64, vp, vp, st, vp]
         lib.qa_continuous_min.argtypes = [pb, vp, C.c_int64, vp, vp, st, vp]
         lib.qa_soft_charge_backward.argtypes = [pb, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -86,7 +87,7 @@ def load():
         lib.qa_optimal_gate_voltages.restype = C.c_int
         lib.qa_virtual_gate_matrix.argtypes = [pb, vp]
         lib.qa_virtual_gate_matrix.restype = C.c_int
-        for f in ("qa_ground_state", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward",
+        for f in ("qa_ground_state", "qa_ground_state_noalloc", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward",
                   "qa_ground_state_batched"):
             getattr(lib, f).restype = C.c_int
         _lib = lib
@@ -150,6 +151,28 @@ def ground_state(cdd, cgd, V, closed=False, nhat=0, t=1.0, precision="fp64", str
                                _stream(stream)))
     del keep
     return (out, st.as_dict()) if stats else out
+
+
+NOALLOC_MAX_PIXELS = 65536
+
+
+def ground_state_noalloc(cdd, cgd, V, out, closed=False, nhat=0, t=1.0, precision="fp64",
+                         stream=None, exhaustive=False):
+    """qa_ground_state_noalloc: the ground state into the caller's int32 (P, N)
+    tensor `out`, with the library's static device scratch (P <= 65536; calls
+    on one GPU must not overlap)."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, 0.0, t, precision,
+                            FLAG_EXHAUSTIVE if exhaustive else 0)
+    V = _device_V(V, pb.n_gate)
+    P = V.shape[0]
+    if (out.dtype != torch.int32 or not out.is_contiguous() or out.device != V.device
+            or tuple(out.shape) != (P, pb.n_dot)):
+        raise QArrayError(2, "out must be a contiguous int32 (P, N) tensor on V's device")
+    _check(lib.qa_ground_state_noalloc(C.byref(pb), C.c_void_p(V.data_ptr()), P,
+                                       C.c_void_p(out.data_ptr()), _stream(stream)))
+    del keep
+    return out
 
 
 def continuous_min(cdd, cgd, V, closed=False, nhat=0, stream=None, stats=False):

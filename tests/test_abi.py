@@ -127,3 +127,21 @@ def test_batched_validation(qa):
     assert st == 2
     assert lib.qa_ground_state_batched(probs, 2, C.c_void_p(16), None, i64(cnt), i64(off),
                                        C.c_void_p(16), None, None, None) == 1
+
+
+def test_noalloc_validation(qa):
+    """The allocation-free ground state validates like qa_ground_state and
+    rejects more pixels than its static scratch holds, before any device
+    work."""
+    lib = qa.load()
+    pb, keep = qa.make_problem(GOOD_CDD, GOOD_CGD)
+    f = lib.qa_ground_state_noalloc
+    assert f(C.byref(pb), C.c_void_p(16), qa.NOALLOC_MAX_PIXELS + 1, C.c_void_p(16), None) == 2
+    assert b"static scratch" in lib.qa_last_error()
+    assert f(C.byref(pb), C.c_void_p(16), -1, C.c_void_p(16), None) == 2
+    assert f(C.byref(pb), None, 0, None, None) == 0
+    assert lib.qa_last_error() == b""
+    assert f(C.byref(pb), None, 4, C.c_void_p(16), None) == 1
+    bad, kb = qa.make_problem(np.array([[1.0, -2.0], [-2.0, 1.0]]), GOOD_CGD)
+    assert f(C.byref(bad), C.c_void_p(16), 4, C.c_void_p(16), None) == 4
+    assert b"positive definite" in lib.qa_last_error()
