@@ -9,7 +9,8 @@ and the FP64 re-score of near ties.  Inputs are resident in HBM before the
 timed region.  Alongside: the FP32 and FP64 scoring forms of the same
 diagram, the double dot and the 4-dot chain (T = 0 and kT = 0.01), the
 fwd+bwd time of the softargmin adjoint (2x4 array with a sensor dot), the
-roofline of the dominant kernel and the FP64 oracle timed on the host.
+roofline of the dominant kernel, and the FP64 oracle timed on the host (its
+references also give every GPU result's mismatch count against it).
 
     python bench.py [--steps K] [--warmup W] [--precision bf16x3]
     python bench.py --mode kernel    # only the headline calls (for rocprofv3)
@@ -36,7 +37,7 @@ PEAK = {  # MI355X published dense peaks
     "bf16x3": 2.5e15, "bf16x2": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12,
 }
 HBM_PEAK = 8.0e12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_score_bound_grid16.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_k_score_bound_grid16.json")
 
 
 def log(*a):
@@ -87,7 +88,8 @@ def direct_soft(qa, cdd, cgd, V, kT, gbar, torch):
     dG = torch.empty((n, g), dtype=torch.float64, device="cuda")
     dV = torch.empty_like(V)
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
-    ptr = [C.c_void_p(t.data_ptr()) for t in (V, nbar, saved, gbar, dC, dG, dV)]
+    ptr = [C.c_void_p(t.data_ptr() if t is not None else 0)
+           for t in (V, nbar, saved, gbar, dC, dG, dV)]
 
     def fwd():
         st = lib.qa_soft_charge(C.byref(pb), ptr[0], P, ptr[1], ptr[2], None, stream)
@@ -116,26 +118,127 @@ def run_copy(torch):
                       "copies": 5}))
 
 
-def cpu_baseline(O, W, budget_s):
-    """O-method (the paper's algorithm in FP64, exact QP) on a seeded sample
-    of the headline diagram's pixels, every host thread."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _mismatch(O, n_gpu, ref):
+    """Pixels whose GPU ground state differs from the oracle's, FP64 ties
+    (gap < 1e-9) and candidate-set boundary pixels excluded; and those
+    excluded."""
+    tie = (ref["e2"] - ref["e1"] < 1e-9)
+    if "info" in ref:
+        tie = tie | ((ref["info"] & O.INFO_AMBIGUOUS) > 0)
+    return int(((n_gpu != ref["n"]).any(1) & ~tie).sum()), int(tie.sum())
+
+
+def cpu_leg(O, W, gpu, threads_note):
+    """The FP64 oracle on the host: its throughput on the headline diagram
+    (O-method, the paper's algorithm with an exact QP, all threads and one
+    thread; O-exact, Schnorr-Euchner enumeration), and, from the references
+    it computes, the accuracy of every GPU result the bench produced."""
     d = W.grid4x4(200)
-    rng = np.random.default_rng(12345)
-    order = rng.permutation(d.P)
-    probe = order[:64]
+    threads = O.max_threads()
+    # O-method over the whole diagram, every host thread
     t0 = time.perf_counter()
-    O.method_gs(d.cdd, d.cgd, d.V[probe])
-    per_px = (time.perf_counter() - t0) / len(probe)
-    n = int(min(d.P - 64, max(64, budget_s / max(per_px, 1e-6))))
-    sample = order[64:64 + n]
-    t0 = time.perf_counter()
-    O.method_gs(d.cdd, d.cgd, d.V[sample])
+    ref = O.method_gs(d.cdd, d.cgd, d.V)
     dt = time.perf_counter() - t0
-    return {"value": len(sample) / dt, "unit": "pixels/s", "cores": O.max_threads(),
-            "kind": "oracle",
-            "sample": "%d seeded random pixels of the 16-dot 100x100 diagram, O-method "
-                      "(FP64, all 65536 candidates per pixel scored directly), %.1f s"
-                      % (len(sample), dt)}
+    # one thread on a seeded sample
+    sample = np.random.default_rng(12345).choice(d.P, 256, replace=False)
+    O.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        O.method_gs(d.cdd, d.cgd, d.V[sample])
+        dt1 = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        O.exact_se(d.cdd, d.cgd, d.V)
+        dte1 = time.perf_counter() - t2
+    finally:
+        O.set_threads(threads)
+    t2 = time.perf_counter()
+    ex = O.exact_se(d.cdd, d.cgd, d.V)
+    dte = time.perf_counter() - t2
+    base = {"value": d.P / dt, "unit": "pixels/s", "cores": threads, "kind": "oracle",
+            "sample": "the whole 16-dot 100x100 diagram (10^4 pixels), O-method (FP64, exact "
+                      "QP, all 65536 candidates per pixel scored directly), %.1f s on %d threads"
+                      % (dt, threads),
+            "value_1thread": len(sample) / dt1,
+            "sample_1thread": "256 seeded pixels of the same diagram, one thread, %.1f s" % dt1,
+            "o_exact_pixels_per_s": d.P / dte,
+            "o_exact_pixels_per_s_1thread": d.P / dte1,
+            "o_exact": "Schnorr-Euchner enumeration of the exact minimiser (no candidate box), "
+                       "the whole diagram",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "threads_note": threads_note}
+    acc = {}
+    miss, ties = _mismatch(O, ex["n"][:, :], ref)
+    acc["headline_method_misses_vs_exact"] = miss
+    for form, n in gpu.get("forms", {}).items():
+        bad, excl = _mismatch(O, n, ref)
+        acc["form " + form] = {"pixels": d.P, "mismatches_vs_oracle": bad, "excluded_ties": excl}
+    for t, n in gpu.get("thresholded", {}).items():
+        dt_ = W.grid4x4(200, t=t)
+        rt = O.method_gs(dt_.cdd, dt_.cgd, dt_.V, t=t)
+        bad, excl = _mismatch(O, n, rt)
+        acc["thresholded t=%.3f" % t] = {
+            "pixels": d.P, "mismatches_vs_oracle_same_t": bad, "excluded_ties": excl,
+            "differs_from_exact (method artefacts, Sec. 3.2.2)":
+                int(((rt["n"] != ex["n"]).any(1) & (ex["e2"] - ex["e1"] >= 1e-9)).sum())}
+    rep = {}
+    for key, (dg, idx, n) in gpu.get("replica", {}).items():
+        r = O.method_gs(dg.cdd, dg.cgd, dg.V[idx], closed=dg.closed, nhat=dg.nhat, t=dg.t)
+        bad, excl = _mismatch(O, n, r)
+        e = {"sampled_pixels": len(idx), "mismatches_vs_oracle": bad, "excluded_ties": excl}
+        if not dg.closed or dg.n_dot <= 10:
+            x = O.exact_se(dg.cdd, dg.cgd, dg.V[idx], closed=dg.closed, nhat=dg.nhat)
+            e["method_misses_vs_exact"] = int(((r["n"] != x["n"]).any(1)
+                                               & (x["e2"] - x["e1"] >= 1e-9)).sum())
+        rep[key] = e
+    if rep:
+        acc["paper_benchmark_replica"] = rep
+    if "batch" in gpu:
+        bad = excl = 0
+        worst = 0.0
+        npx = 0
+        for dg, n, nbar in gpu["batch"]:
+            r = O.method_gs(dg.cdd, dg.cgd, dg.V, closed=dg.closed, nhat=dg.nhat, t=dg.t)
+            b_, e_ = _mismatch(O, n, r)
+            bad, excl, npx = bad + b_, excl + e_, npx + dg.P
+            if dg.kT > 0:
+                tie = (r["e2"] - r["e1"] < 1e-9) | ((r["info"] & O.INFO_AMBIGUOUS) > 0)
+                rs, _, _ = O.method_soft(dg.cdd, dg.cgd, dg.V, closed=dg.closed, nhat=dg.nhat,
+                                         t=dg.t, kT=dg.kT)
+                err = (np.abs(nbar - rs) / np.maximum(1, np.abs(rs)))[~tie]
+                worst = max(worst, float(err.max(initial=0)))
+        acc["ragged_batch_subset"] = {"diagrams": len(gpu["batch"]), "pixels": npx,
+                                      "mismatches_vs_oracle": bad, "excluded_ties": excl,
+                                      "max_scaled_soft_error": worst}
+    if "adjoint" in gpu:
+        a, gbar, grads = gpu["adjoint"]
+        st = O.method_setup(a.cdd[:8, :8], a.cgd[:8, :], a.V)
+        refg = O.soft_grad(a.cdd[:8, :8], a.cgd[:8, :], a.V, a.kT, st["n0"], st["freemask"],
+                           st["k"], gbar)
+        acc["adjoint_relative_error"] = {
+            name: float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300))
+            for name, g, r in zip(("dC_dd", "dC_gd", "dV"), grads, refg)}
+    return base, acc
+
+
+def counters_entry(args):
+    """Counter figures of the dominant kernel from the committed rocprofv3
+    summary, when they were taken on the current scorer source and form."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    tr = json.load(open(COUNTERS_FILE))
+    src = os.path.join(ROOT, "paper_2404_04994_amd", "csrc", "qa_mfma.hip")
+    if tr.get("source_sha") != sha(src) or tr.get("precision") != args.precision or args.exhaustive:
+        return None
+    return tr
 
 
 def main():
@@ -145,7 +248,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x2", "fp32", "fp64"])
     ap.add_argument("--mode", default="bench", choices=["bench", "kernel", "adjoint", "batch", "copy"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--batch-diagrams", type=int, default=4096)
@@ -196,89 +298,69 @@ def main():
 
     # ---------------- headline ----------------
     log("headline: warmup %d, steps %d, precision %s" % (args.warmup, args.steps, args.precision))
-    # timed region 1: throughput (direct launches on the current stream)
+    # timed region: throughput (direct launches on the current stream)
     wall = timed_calls(call, args.steps, args.warmup, torch)
     value = d.P * args.steps / wall
     ms_step = 1e3 * wall / args.steps
-    # timed region 2: the same steps with HIP events around every stage on
-    # the stream the kernels run on (direct launches)
-    qa.timing_enable(True)
-    for _ in range(3):
-        call()
-    torch.cuda.synchronize()
-    qa.timing_reset()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        call()
-    torch.cuda.synchronize()
-    wall_ev = time.perf_counter() - t0
-    stage_ms, ncalls = qa.timing_sum()
-    qa.timing_enable(False)
-    stage_avg = [s / max(ncalls, 1) for s in stage_ms]
-    log("headline %.4g px/s, %.4f ms/step, %.4f ms/step with stage events; stages "
-        "(setup, score, rescore) ms %s" % (value, ms_step, 1e3 * wall_ev / args.steps,
-                                           ["%.4f" % s for s in stage_avg]))
-
-    # stats and accuracy of the headline form against the oracle on a sample
+    # per-kernel durations: HIP events on the stream the kernels run on,
+    # around back-to-back launches of each kernel
+    setup_ms, score_ms = qa.time_kernels(d.cdd, d.cgd, V, out, max(20, args.steps),
+                                         precision=args.precision, exhaustive=args.exhaustive)
+    log("headline %.4g px/s, %.4f ms/step; setup kernel %.2f us, scorer %.2f us"
+        % (value, ms_step, 1e3 * setup_ms, 1e3 * score_ms))
     n_gpu, st = qa.ground_state(d.cdd, d.cgd, V, precision=args.precision, stats=True,
                                 exhaustive=args.exhaustive)
-    n_gpu = n_gpu.cpu().numpy()
-    accuracy = {"stats": st}
-    try:
-        import oracle as O
-        O.build()
-        idx = np.random.default_rng(7).choice(d.P, 200, replace=False)
-        ref = O.method_gs(d.cdd, d.cgd, d.V[idx])
-        tie = (ref["e2"] - ref["e1"] < 1e-9) | ((ref["info"] & O.INFO_AMBIGUOUS) > 0)
-        bad = ((n_gpu[idx] != ref["n"]).any(1) & ~tie).sum()
-        ex = O.exact_se(d.cdd, d.cgd, d.V[idx])
-        miss = ((ex["n"] != ref["n"]).any(1) & ~tie).sum()
-        accuracy.update({"oracle_sampled_pixels": 200, "mismatches_vs_method": int(bad),
-                         "fp64_ties_excluded": int(tie.sum()),
-                         "method_misses_vs_exact": int(miss)})
-    except Exception as e:  # the oracle is test infrastructure; report and go on
-        accuracy["oracle_error"] = repr(e)
+    gpu = {"forms": {args.precision + ("_exhaustive" if args.exhaustive else ""):
+                     n_gpu.cpu().numpy()}}
 
     # ---------------- roofline of the dominant kernel ----------------
     # The scorer searches the 2^16 box in bound order and computes the energy
     # of st["scored"] states (the rest are ruled out by the lower bound); its
     # algorithmic work is the b^T g contraction of those states, N
-    # multiply-adds each.  The dense-box equivalent (all 2^16 states) is
-    # reported beside it, labelled as such.
-    score_s = stage_avg[1] * 1e-3
+    # multiply-adds each, on the matrix cores: the roofline is the matrix-core
+    # peak of the form's dtype.  What limits the kernel below that roofline
+    # comes from its counters (rocprofv3 summary under profiles/).
+    score_s = score_ms * 1e-3
     flops = 2.0 * d.n_dot * st["scored"]
     dense_flops = 2.0 * d.n_dot * (2 ** d.n_dot) * d.P
     achieved = flops / score_s / 1e12
     peak = PEAK[args.precision] / 1e12
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        src = os.path.join(ROOT, "paper_2404_04994_amd", "csrc", "qa_mfma.hip")
-        if (tr.get("source_sha") == sha(src) and tr.get("precision") == args.precision
-                and not args.exhaustive):
-            traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
+    ctr = counters_entry(args)
+    roofline = {"bound": "mfma" if args.precision != "fp64" else "alu",
+                "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
+                "traffic": ctr.get("bytes_per_launch") if ctr else None,
                 "kernel": ("k_score_fp64<6,16>" if args.precision == "fp64" else
                            ("k_score_mfma<%s, dense>" if args.exhaustive else "k_score_bound<%s>")
                            % args.precision),
-                "kernel_avg_us": round(stage_avg[1] * 1e3, 3),
+                "kernel_avg_us": round(score_ms * 1e3, 3),
+                "kernel_timing": "HIP events on the kernel's stream around %d back-to-back "
+                                 "launches (qa_time_kernels)" % max(20, args.steps),
+                "setup_kernel_avg_us": round(setup_ms * 1e3, 3),
                 "algorithmic_flops_per_launch": flops,
                 "states_scored_per_launch": st["scored"],
                 "candidate_states_per_launch": st["candidates"],
                 "dense_box_equivalent_TFLOPs": round(dense_flops / score_s / 1e12, 3)}
+    if ctr:
+        for k in ("limiter", "valu_busy_frac", "mfma_busy_frac", "valu_insts_per_pixel",
+                  "mfma_insts_per_pixel", "salu_insts_per_pixel", "counter_kernel_us"):
+            if k in ctr:
+                roofline[k] = ctr[k]
 
     extras = {}
     if not args.no_extras:
-        extras = run_extras(qa, W, torch, d, V, out, args)
+        extras = run_extras(qa, W, torch, d, V, out, args, gpu)
 
-    cpu = None
+    cpu, accuracy = None, {"stats": st}
     if not args.no_cpu:
         try:
             import oracle as O
-            cpu = cpu_baseline(O, W, args.cpu_seconds)
-            log("cpu baseline %.4g px/s on %d threads" % (cpu["value"], cpu["cores"]))
-        except Exception as e:
+            O.build()
+            cpu, acc = cpu_leg(O, W, gpu, "OpenMP over pixels; every host thread unless noted")
+            accuracy.update(acc)
+            log("cpu baseline %.4g px/s on %d threads (1 thread %.4g px/s)"
+                % (cpu["value"], cpu["cores"], cpu["value_1thread"]))
+        except Exception as e:  # the oracle is test infrastructure; report and go on
             cpu = {"error": repr(e)}
 
     line = {
@@ -289,9 +371,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "open 16-dot 4x4 array, 100x100 virtual-gate sweep (T = 0, default "
                                "2^16 box, seed 200)",
-                   "n_dot": 16, "n_gate": 16, "pixels": d.P, "precision": args.precision,
-                   "stage_ms": [round(s, 5) for s in stage_avg],
-                   "ms_per_step_with_stage_events": round(1e3 * wall_ev / args.steps, 5)},
+                   "n_dot": 16, "n_gate": 16, "pixels": d.P, "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
@@ -302,29 +382,23 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def run_extras(qa, W, torch, d, V, out, args):
+def run_extras(qa, W, torch, d, V, out, args, gpu):
+    """The other workloads; their GPU outputs go into `gpu` for the oracle
+    comparison of the CPU leg."""
     res = {}
     steps = max(10, args.steps // 4)
     # other scoring forms of the same diagram
     forms = {}
-    for prec in ("bf16x3", "bf16x2", "fp32", "fp64"):
-        call = direct_gs(qa, d, V, out, prec, torch)
+    for prec, exh in (("bf16x3", False), ("bf16x2", False), ("fp32", False), ("fp64", False),
+                      ("bf16x3", True), ("fp32", True)):
+        key = prec + ("_exhaustive" if exh else "")
+        call = direct_gs(qa, d, V, out, prec, torch, flags=qa.FLAG_EXHAUSTIVE if exh else 0)
         n = steps if prec != "fp64" else max(5, steps // 10)
         wall = timed_calls(call, n, 3, torch)
-        _, st = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True)
-        forms[prec] = {"pixels_per_s": round(d.P * n / wall, 1),
-                       "ms_per_diagram": round(1e3 * wall / n, 4),
-                       "near_tie_pixels": st["near_tie_pixels"],
-                       "states_scored_per_pixel": round(st["scored"] / d.P, 1)}
-        log("form %s: %s" % (prec, forms[prec]))
-    # the exhaustive matrix-core scorer (every state of the box) for reference
-    for prec in ("bf16x3", "fp32"):
-        call = direct_gs(qa, d, V, out, prec, torch, flags=qa.FLAG_EXHAUSTIVE)
-        wall = timed_calls(call, steps, 3, torch)
-        _, st = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, exhaustive=True)
-        key = prec + "_exhaustive"
-        forms[key] = {"pixels_per_s": round(d.P * steps / wall, 1),
-                      "ms_per_diagram": round(1e3 * wall / steps, 4),
+        ng, st = qa.ground_state(d.cdd, d.cgd, V, precision=prec, stats=True, exhaustive=exh)
+        gpu["forms"][key] = ng.cpu().numpy()
+        forms[key] = {"pixels_per_s": round(d.P * n / wall, 1),
+                      "ms_per_diagram": round(1e3 * wall / n, 4),
                       "near_tie_pixels": st["near_tie_pixels"],
                       "states_scored_per_pixel": round(st["scored"] / d.P, 1)}
         log("form %s: %s" % (key, forms[key]))
@@ -332,27 +406,19 @@ def run_extras(qa, W, torch, d, V, out, args):
     # thresholded candidate sets of the same diagram (Sec. 3.2.2): the
     # headline form (sub-box per pixel on the matrix cores) and FP64 scoring
     pruned = {}
+    gpu["thresholded"] = {}
     for t in (2 / 3, 1 / 2, 1 / 3):
         dt = W.grid4x4(200, t=t)
         nt = max(5, steps // 4)
         wall64 = timed_calls(direct_gs(qa, dt, V, out, "fp64", torch), nt, 2, torch)
         wall = timed_calls(direct_gs(qa, dt, V, out, args.precision, torch), nt, 2, torch)
-        _, st = qa.ground_state(dt.cdd, dt.cgd, V, t=t, precision=args.precision, stats=True)
-        entry = {"pixels_per_s": round(dt.P * nt / wall, 1),
-                 "pixels_per_s_fp64": round(dt.P * nt / wall64, 1),
-                 "mean_candidates": round(st["candidates"] / dt.P, 1),
-                 "near_tie_pixels": st["near_tie_pixels"]}
-        try:
-            import oracle as O
-            idx = np.random.default_rng(3).choice(dt.P, 200, replace=False)
-            nt = out.cpu().numpy()[idx]
-            ex = O.exact_se(dt.cdd, dt.cgd, dt.V[idx])
-            tie = ex["e2"] - ex["e1"] < 1e-9
-            entry["differs_from_exact_sampled"] = "%d/200" % int(((nt != ex["n"]).any(1) & ~tie).sum())
-        except Exception as e:
-            entry["oracle_error"] = repr(e)
-        pruned["t=%.3f" % t] = entry
-        log("pruned t=%.3f: %s" % (t, entry))
+        ng, st = qa.ground_state(dt.cdd, dt.cgd, V, t=t, precision=args.precision, stats=True)
+        gpu["thresholded"][t] = ng.cpu().numpy()
+        pruned["t=%.3f" % t] = {"pixels_per_s": round(dt.P * nt / wall, 1),
+                                "pixels_per_s_fp64": round(dt.P * nt / wall64, 1),
+                                "mean_candidates": round(st["candidates"] / dt.P, 1),
+                                "near_tie_pixels": st["near_tie_pixels"]}
+        log("pruned t=%.3f: %s" % (t, pruned["t=%.3f" % t]))
     res["thresholded_16dot"] = pruned
     # the small workloads
     small = {}
@@ -364,8 +430,7 @@ def run_extras(qa, W, torch, d, V, out, args):
             o = torch.empty((dg.P, dg.n_dot), dtype=torch.int32, device="cuda")
             call = direct_gs(qa, dg, Vd, o, "fp64", torch)
         else:
-            def call(dg=dg, Vd=Vd):
-                qa.soft_charge(dg.cdd, dg.cgd, Vd, kT)
+            call, _ = direct_soft(qa, dg.cdd, dg.cgd, Vd, kT, None, torch)
         wall = timed_calls(call, steps, 3, torch)
         small[name] = {"pixels_per_s": round(dg.P * steps / wall, 1),
                        "ms_per_diagram": round(1e3 * wall / steps, 4)}
@@ -374,9 +439,10 @@ def run_extras(qa, W, torch, d, V, out, args):
     # the paper's own benchmark (Sec. 7): random uniform capacitances in
     # Maxwell form, 100 x 100 random gate voltages, N = 1..16, open and closed
     # with as many carriers as dots; and the threshold sweep of its second
-    # figure.  ms per diagram, headline form for open N >= 9, FP64 elsewhere.
+    # figure.  ms per diagram, headline form for N >= 9, FP64 below.
     replica = {}
-    for n in (1, 2, 3, 4, 6, 8, 10, 12, 14, 16):
+    gpu["replica"] = {}
+    for n in range(1, 17):
         entry = {}
         for closed in (False, True):
             dg = W.paper_replica(n, seed=500 + n, closed=closed)
@@ -384,6 +450,9 @@ def run_extras(qa, W, torch, d, V, out, args):
             o = torch.empty((dg.P, dg.n_dot), dtype=torch.int32, device="cuda")
             wall = timed_calls(direct_gs(qa, dg, Vr, o, args.precision, torch), 10, 2, torch)
             entry["closed_ms" if closed else "open_ms"] = round(1e3 * wall / 10, 4)
+            idx = np.random.default_rng(n + 100 * closed).choice(dg.P, 400, replace=False)
+            gpu["replica"]["N=%d %s" % (n, "closed" if closed else "open")] = (
+                dg, idx, o.cpu().numpy()[idx])
         replica["N=%d" % n] = entry
     log("paper benchmark replica (ms per 100x100 diagram): %s" % replica)
     sweep = {}
@@ -399,8 +468,9 @@ def run_extras(qa, W, torch, d, V, out, args):
                     1e3 * wall / 10, 4)
     log("threshold sweep (ms per diagram): %s" % sweep)
     res["paper_benchmark_replica"] = {"ms_per_diagram": replica, "threshold_sweep_ms": sweep,
-                                      "inputs": "random_maxwell capacitances, V ~ U[-1, 2]^N, "
-                                                "seed 500 + N"}
+                                      "inputs": "random_maxwell capacitances (every element of "
+                                                "the dot and gate capacitance matrix U[0,1), "
+                                                "Maxwell form), V ~ U[-1, 2]^N, seed 500 + N"}
     # adjoint: 2x4 array + sensor dot, kT = 0.02, forward + backward
     a = W.adjoint_case(400)
     Va = torch.as_tensor(a.V, device="cuda")
@@ -410,6 +480,8 @@ def run_extras(qa, W, torch, d, V, out, args):
     fwd_d, fwdbwd_d = direct_soft(qa, cdd8, cgd8, Va, a.kT, gb, torch)
     wf = timed_calls(fwd_d, steps, 3, torch)
     wb = timed_calls(fwdbwd_d, steps, 3, torch)
+    _, _, _, _, dC, dG, dV = fwdbwd_d.keep
+    gpu["adjoint"] = (a, gb.cpu().numpy(), (dC.cpu().numpy(), dG.cpu().numpy(), dV.cpu().numpy()))
 
     def fwdbwd_py():  # through the Python wrappers (tensor allocation per call)
         nb, saved = qa.soft_charge(cdd8, cgd8, Va, a.kT)
@@ -479,7 +551,8 @@ def run_extras(qa, W, torch, d, V, out, args):
     # ragged dataset batch: 4096 diagrams of 2..8 dots, 64 x 64 pixels each
     if args.batch_diagrams > 0:
         t0 = time.perf_counter()
-        b = qa.Batch(W.ragged_batch(args.batch_diagrams, npix=64))
+        ds = W.ragged_batch(args.batch_diagrams, npix=64)
+        b = qa.Batch(ds)
         log("batch of %d diagrams packed in %.1f s" % (args.batch_diagrams, time.perf_counter() - t0))
         b.run()  # first call: autotune
         torch.cuda.synchronize()
@@ -497,6 +570,13 @@ def run_extras(qa, W, torch, d, V, out, args):
                                "diagrams_per_s": round(args.batch_diagrams * nb / wall, 1),
                                "candidates": st["candidates"], "qp_pixels": st["qp_pixels"]}
         log("ragged batch: %s" % res["ragged_batch"])
+        # a seeded 64-diagram subset for the oracle comparison
+        n_all, nbar_all = b.n.cpu().numpy(), b.nbar.cpu().numpy()
+        gpu["batch"] = []
+        for i in np.random.default_rng(31).choice(len(ds), min(64, len(ds)), replace=False):
+            dg, o = ds[i], int(b.out_offsets[i])
+            gpu["batch"].append((dg, n_all[o:o + dg.P * dg.n_dot].reshape(dg.P, dg.n_dot),
+                                 nbar_all[o:o + dg.P * dg.n_dot].reshape(dg.P, dg.n_dot)))
         del b
     return res
 

@@ -254,6 +254,18 @@ void qa_graphs_enable(int on);
 void qa_timing_reset(void *hip_stream);
 qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out);
 
+/* Kernel timing (diagnostics).  Runs qa_ground_state's device work once
+ * (n_out_dev receives the ground state), then on hip_stream: an event,
+ * `reps` back-to-back launches of the setup kernel (prologue, continuous
+ * minimum, candidate setup), an event, `reps` back-to-back launches of the
+ * T = 0 scorer the problem selects, an event.  Waits, and writes the mean
+ * milliseconds per launch: ms_out[0] the setup kernel, ms_out[1] the scorer.
+ * No events separate launches of one kernel, so the mean is the kernel's
+ * duration plus the dispatch gap between back-to-back launches.
+ * reps in [1, 100000]; P >= 1. */
+qa_status qa_time_kernels(const qa_problem *prob, const double *V_dev, int64_t P,
+                          int32_t *n_out_dev, int32_t reps, double *ms_out, void *hip_stream);
+
 /* Charge sensors (Sec. 5.1).  The problem's last n_sensor dots are sensor
  * dots (prob: the whole system, n_dot = N_array + n_sensor).  The array
  * dots' charges are given: their ground state or softargmin computed by the

@@ -298,6 +298,18 @@ int scorer_mode(const qa_problem *pb)
     return pb->mode == QA_CLOSED ? 2 : (pb->threshold < 1.0 ? 1 : 0);
 }
 
+// the T = 0 scorer of the problem's candidate family and precision
+hipError_t launch_scorer(const DiagRec *dr, const PixRec *pr, int64_t *counters,
+                         const qa_problem *pb, int64_t P, int32_t *n_out, hipStream_t s)
+{
+    if (use_matrix_cores(pb))
+        return launch_score_mfma(dr, pr, P, pb->precision, scorer_mode(pb),
+                                 (pb->flags & QA_FLAG_EXHAUSTIVE) != 0, n_out, counters,
+                                 pb->n_dot, s);
+    if (pb->n_dot <= 8) return launch_score_tab(dr, pr, P, n_out, counters, pb->n_dot, s);
+    return launch_score_fp64(dr, pr, P, n_out, counters, pb->n_dot, s);
+}
+
 // The device work of one single-diagram call on stream s, with the inputs
 // already in dr: prologue, setup and QP in one kernel, then either the T = 0
 // scoring (n_out) or the softargmin (nbar, saved).  pr holds P pixel records,
@@ -310,17 +322,10 @@ qa_status enqueue_path(DiagRec *dr, PixRec *pr, int64_t *counters, int32_t *bsta
     if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
     QA_HIP(launch_setup(dr, V, P, pr, counters, bstats, pb->n_dot, closed, s));
     if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
-    if (nbar) {
+    if (nbar)
         QA_HIP(launch_soft_fwd(dr, pr, P, nbar, saved, counters, pb->n_dot, s));
-    } else if (use_matrix_cores(pb)) {
-        QA_HIP(launch_score_mfma(dr, pr, P, pb->precision, scorer_mode(pb),
-                                 (pb->flags & QA_FLAG_EXHAUSTIVE) != 0, n_out, counters,
-                                 pb->n_dot, s));
-    } else if (pb->n_dot <= 8) {
-        QA_HIP(launch_score_tab(dr, pr, P, n_out, counters, pb->n_dot, s));
-    } else {
-        QA_HIP(launch_score_fp64(dr, pr, P, n_out, counters, pb->n_dot, s));
-    }
+    else
+        QA_HIP(launch_scorer(dr, pr, counters, pb, P, n_out, s));
     if (ev) QA_HIP(hipEventRecord((*ev)[2], s));
     if (ev) QA_HIP(hipEventRecord((*ev)[3], s));
     return QA_OK;
@@ -889,6 +894,51 @@ qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out)
     for (int s = 0; s < 3; ++s) ms_out[s] = acc[s];
     if (calls_out) *calls_out = w->ev_used;
     return QA_OK;
+}
+
+qa_status qa_time_kernels(const qa_problem *prob, const double *V_dev, int64_t P,
+                          int32_t *n_out_dev, int32_t reps, double *ms_out, void *hip_stream)
+{
+    clear_error();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    if (P < 1 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [1, 2^31)", (long long)P);
+    if (reps < 1 || reps > 100000) return fail(QA_E_RANGE, "reps=%d outside [1, 1e5]", reps);
+    if (!V_dev || !n_out_dev || !ms_out) return fail(QA_E_NULL, "V_dev, n_out_dev or ms_out is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    if ((st = grow_single(w, P))) return st;
+    if ((st = upload_diag(w, prob))) return st;
+    w->bstats_used = setup_blocks(P, prob->n_dot);
+    const hipStream_t s = w->stream;
+    // one whole call first: the records the repeated launches read
+    if ((st = enqueue_single(w, s, prob, V_dev, P, n_out_dev, nullptr, nullptr, nullptr)))
+        return st;
+    hipEvent_t ev[3] = {};
+    for (auto &e : ev) QA_HIP(hipEventCreate(&e));
+    auto done = [&](qa_status r) {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        return r;
+    };
+    if (hipEventRecord(ev[0], s) != hipSuccess) return done(fail(QA_E_DEVICE, "event record failed"));
+    for (int r = 0; r < reps; ++r)
+        if (launch_setup(w->dr, V_dev, P, w->pr, w->counters, w->bstats, prob->n_dot,
+                         prob->mode == QA_CLOSED, s) != hipSuccess)
+            return done(fail(QA_E_DEVICE, "setup launch failed"));
+    if (hipEventRecord(ev[1], s) != hipSuccess) return done(fail(QA_E_DEVICE, "event record failed"));
+    for (int r = 0; r < reps; ++r)
+        if (launch_scorer(w->dr, w->pr, w->counters, prob, P, n_out_dev, s) != hipSuccess)
+            return done(fail(QA_E_DEVICE, "scorer launch failed"));
+    if (hipEventRecord(ev[2], s) != hipSuccess) return done(fail(QA_E_DEVICE, "event record failed"));
+    if (hipEventSynchronize(ev[2]) != hipSuccess)
+        return done(fail(QA_E_DEVICE, "event synchronize failed"));
+    float t01 = 0.0f, t12 = 0.0f;
+    if (hipEventElapsedTime(&t01, ev[0], ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&t12, ev[1], ev[2]) != hipSuccess)
+        return done(fail(QA_E_DEVICE, "event elapsed time failed"));
+    ms_out[0] = t01 / reps;
+    ms_out[1] = t12 / reps;
+    return done(QA_OK);
 }
 
 const char *qa_last_error(void) { return g_err; }

@@ -22,7 +22,8 @@ STATUS = {0: "QA_OK", 1: "QA_E_NULL", 2: "QA_E_SHAPE", 3: "QA_E_NOT_SYMMETRIC", 
           5: "QA_E_RANGE", 6: "QA_E_UNSUPPORTED", 7: "QA_E_WORKSPACE", 8: "QA_E_DEVICE"}
 EXPORTS = ("qa_ground_state", "qa_ground_state_noalloc", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
            "qa_ground_state_batched", "qa_last_error", "qa_release", "qa_version",
-           "qa_timing_enable", "qa_timing_reset", "qa_timing_sum", "qa_graphs_enable")
+           "qa_timing_enable", "qa_timing_reset", "qa_timing_sum", "qa_graphs_enable",
+           "qa_time_kernels")
 
 
 class QArrayError(RuntimeError):
@@ -79,6 +80,8 @@ def load():
         lib.qa_timing_reset.argtypes = [vp]
         lib.qa_timing_sum.argtypes = [vp, C.POINTER(C.c_double), i64p]
         lib.qa_timing_sum.restype = C.c_int
+        lib.qa_time_kernels.argtypes = [pb, vp, C.c_int64, vp, C.c_int32, C.POINTER(C.c_double), vp]
+        lib.qa_time_kernels.restype = C.c_int
         lib.qa_sensor_response.argtypes = [pb, C.POINTER(Sensor), vp, C.c_int64, vp, vp, vp, vp, vp]
         lib.qa_sensor_response.restype = C.c_int
         lib.qa_sensor_noise_len.argtypes = [C.c_int64, C.c_int32, C.c_int32]
@@ -404,6 +407,20 @@ def timing_sum(stream=None):
     calls = C.c_int64(0)
     _check(load().qa_timing_sum(_stream(stream), ms, C.byref(calls)))
     return [ms[0], ms[1], ms[2]], int(calls.value)
+
+
+def time_kernels(cdd, cgd, V, out, reps, t=1.0, precision="fp64", exhaustive=False, stream=None):
+    """qa_time_kernels: mean ms per launch of (the setup kernel, the scorer),
+    each over `reps` back-to-back launches between HIP events on the stream;
+    `out` (int32 (P, N)) receives the ground state."""
+    pb, keep = make_problem(cdd, cgd, False, 0, 0.0, t, precision,
+                            FLAG_EXHAUSTIVE if exhaustive else 0)
+    V = _device_V(V, pb.n_gate)
+    ms = (C.c_double * 2)()
+    _check(load().qa_time_kernels(C.byref(pb), C.c_void_p(V.data_ptr()), V.shape[0],
+                                  C.c_void_p(out.data_ptr()), int(reps), ms, _stream(stream)))
+    del keep
+    return ms[0], ms[1]
 
 
 def release(stream=None):
