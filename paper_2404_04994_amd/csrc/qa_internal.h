@@ -169,6 +169,7 @@ struct alignas(8) PixRec {
     float s[8];
     float K;
     float mu;             // closed: -1^T A_LL^{-1} g_lo (the low sum of the free minimiser)
+    float eg;             // N = 16 lanes: U(n0 + guess) - U(n0), from FP64
 };
 
 struct alignas(8) SavedRec {

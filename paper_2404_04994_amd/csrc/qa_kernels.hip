@@ -420,6 +420,18 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             g0 += sA[q * kMaxDot + dot] * group_bcast<NM, q>(z, base);
         });
         const double u0 = 0.5 * group_dsum<NM>(z * g0);
+        // energy of the guess state n0 + b (b = the bits gm) relative to
+        // U(n0): b^T g0 + 1/2 b^T A b, with (A b)_dot the sum of the columns
+        // of A that b raises
+        double eg = 0.0;
+        if (NM == 16 && n >= 13) {
+            double ab = 0.0;
+            static_for_dev<0, NM>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                ab += (gm >> q & 1u) ? sA[q * kMaxDot + dot] : 0.0;
+            });
+            eg = group_dsum<NM>((gm >> dot & 1u) ? g0 + 0.5 * ab : 0.0);
+        }
         // terms of the lower bound of the bound-ordered scorer (N >= 13):
         // s = S z_hi and K = 1/2 z_hi^T s - U(n0) with S = (C_dd,HH)^{-1};
         // closed arrays also mu = -1^T A_LL^{-1} g0_lo
@@ -451,6 +463,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             if (dot == 0) {
                 o->K = (float)Kb;
                 o->mu = (float)mu;
+                o->eg = (float)eg;
                 o->u0 = u0;
                 o->free = fm;
                 o->k = k;

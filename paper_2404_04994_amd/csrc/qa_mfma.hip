@@ -59,6 +59,43 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi)
     return (fbits(lo) >> 16) | (fbits(hi) & 0xFFFF0000u);
 }
 
+// sum over each 16-lane row (every lane of the row gets it; the exchanges
+// pair lanes symmetrically, so the lanes' sums are identical)
+__device__ __forceinline__ float row_sumf(float x)
+{
+    x += dppf<kDppXor1>(x);
+    x += dppf<kDppXor2>(x);
+    x += dppf<kDppHalfMirror>(x);
+    return x + dppf<kDppMirror>(x);
+}
+
+// bitwise OR over the 64 lanes (every lane gets it)
+__device__ __forceinline__ uint32_t wave_or32(uint32_t x)
+{
+    x |= dpp32<kDppXor1>(x);
+    x |= dpp32<kDppXor2>(x);
+    x |= dpp32<kDppHalfMirror>(x);
+    x |= dpp32<kDppMirror>(x);
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    x = r[0] | r[1];
+    const auto t = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return __builtin_amdgcn_readfirstlane(t[0] | t[1]);
+}
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x)
+{
+    return (uint64_t)wave_or32((uint32_t)x) | ((uint64_t)wave_or32((uint32_t)(x >> 32)) << 32);
+}
+
+// compile-time loop: f(integral_constant<int, I>) for I in [I0, I1)
+template <int I0, int I1, typename Fn>
+__device__ __forceinline__ void sfor(Fn &&f)
+{
+    if constexpr (I0 < I1) {
+        f(std::integral_constant<int, I0>{});
+        sfor<I0 + 1, I1>(f);
+    }
+}
+
 // LDS writes of a wave made visible to all of its lanes (requests of one
 // wave are served in order; the fences keep the compiler from moving them)
 __device__ __forceinline__ void wave_sync()
@@ -73,6 +110,16 @@ constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
 
 #ifndef QA_SCORER_WAVES
 #define QA_SCORER_WAVES 3
+#endif
+// waves per SIMD of the bound-ordered scorer (measured): five for the FP32
+// dense box, four otherwise (the split-BF16 forms read their column
+// operands from LDS once per product, and a fifth wave per SIMD costs more
+// in LDS bandwidth than it hides)
+#ifndef QA_BOUND_WAVES
+#define QA_BOUND_WAVES(PREC, MODE) ((MODE) == kDense && (PREC) == kPrecFP32 ? 5 : 4)
+#endif
+#ifndef QA_BOUND_B_LDS
+#define QA_BOUND_B_LDS 1
 #endif
 
 // MODE kDense: the floor/ceil box.  kPruned: the thresholded candidate set
@@ -550,15 +597,25 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_mfma(const DiagR
 // a margin that covers the FP32 error of the bound and three times the
 // certified error band) holds neither the exact argmin nor any state of the
 // near-tie band.  The upper bound is the energy of the setup's guess (a state
-// of the candidate set) or, when that leaves more than two tiles of rows, the
-// best of the row tile with the smallest bound, scored first.  The rows are
-// scored sixteen to a tile (a row of the tile is any high index); the rest of
-// the kernel (error band, FP64 re-score of near ties) is that of the
-// exhaustive scorer over the scored rows.  The result is the argmin over the
-// whole candidate set, as in the exhaustive form.
+// of the candidate set, its energy computed by the setup in FP64) or, when
+// that leaves more than two tiles of rows, the best of the row tile with the
+// smallest bound, scored first.  The rows are scored sixteen to a tile (a row
+// of the tile is any high index); the next tile's table reads are issued
+// while a tile is on the matrix cores.  Each lane keeps the three smallest
+// minima over groups of four column tiles (16 elements) and where the first
+// two lie; the winner's group is recomputed for the position and the
+// runner-up.  Near ties re-score in FP64 the in-band states of the groups
+// that can hold them (the lanes' two best groups when no lane has a third
+// group in the band, else every scored tile).  The error band and the FP64
+// re-score are those of the exhaustive scorer over the scored rows, so the
+// result is the argmin over the whole candidate set, as in the exhaustive
+// form.  Per pixel the kernel is a chain of dependent steps (LDS reads,
+// cross-lane reductions, matrix products), so several waves share a SIMD;
+// the column operands sit in an LDS table (one read per product) so that
+// the registers allow four or five waves.
 // ---------------------------------------------------------------------------
 template <int PREC, int MODE>
-__global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const DiagRec *__restrict__ dr,
+__global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound(const DiagRec *__restrict__ dr,
                                                      const PixRec *__restrict__ pr, int64_t P,
                                                      int32_t *__restrict__ n_out,
                                                      int64_t *__restrict__ counters)
@@ -573,9 +630,34 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
     __shared__ double sT1d[16][8], sT2d[16][8];  // FP64 tables of the near-tie re-score
     __shared__ double sHd[256], sLd[256];
     __shared__ double sG64[4][kMaxDot];
-    __shared__ uint2 sCt[4][256];                // per wave: C(c_hi) of its pixel (BF16 parts / FP32)
+    __shared__ float sPt[4][32];                 // per wave: b_hi^T g_hi over bits 0..3 / 4..7
+    __shared__ float sWin[4][16];                // per wave: the winning lane's group
     __shared__ uint8_t sList[4][256];            // per wave: high index of every scored row
+    __shared__ uint32_t sBand[4][128];           // per wave: near-tie states to re-score
+    __shared__ uint4 sB[16][64];                 // column operands: [column tile][lane]
     __shared__ unsigned long long sflag, sgap, srows, scand;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int q = lane >> 4;
+    const int mrow = lane & 15;
+    const int li = lane & 15;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // the first pixel's record, requested before the tables are staged:
+    // lane i < 16 holds g0_i and n0_i, lanes 8..15 also s_{i-8}, lane 0 K,
+    // lane 1 mu (vector loads, one pixel ahead from here on)
+    double gnext = 0.0;
+    int nnext = 0, knext = 0;
+    uint32_t fnext = 0;
+    float snext = 0.0f, egnext = 0.0f;
+    if (wave < P) {
+        gnext = pr[wave].g0[li];
+        nnext = pr[wave].n0[li];
+        snext = (li >= 8) ? pr[wave].s[li - 8] : (li == 1 ? pr[wave].mu : pr[wave].K);
+        if (PRUNED) fnext = pr[wave].free;
+        if (CLOSED) knext = pr[wave].k;
+        egnext = pr[wave].eg;
+    }
     const int n = dr->n;
     const int nh = n - 8;
     const int nrt = 1 << (nh - 4);
@@ -593,12 +675,6 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         sHlo[e] = dr->hlo[e];
     }
     if (threadIdx.x == 0) { sflag = 0; sgap = 0; srows = 0; scand = 0; }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int q = lane >> 4;
-    const int mrow = lane & 15;
-    const int li = lane & 15;
     const float sumabs = dr->sumabs;
     const float hsabs = dr->sabsS;
     // closed arrays: w and 1 / (2 gamma) of the low-sum term of the bound
@@ -610,36 +686,51 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         wabs += fabsf(wb[j]);
     }
     const float inv2g = CLOSED ? dr->inv2g : 0.0f;
+    __syncthreads();
 
-    // pixel-independent column operands (as in the dense scorer)
-    uint32_t bw[16][4];
-    float bf[16][3];
-#pragma unroll
-    for (int ct = 0; ct < 16; ++ct) {
+    // pixel-independent column operands (as in the dense scorer), from the
+    // staged h_lo table: the B operand of column tile ct for this lane
+    auto col_operand = [&](int ct) -> uint4 {
         const int clo = ct * 16 + mrow;
-        const float h = dr->hlo[clo];
+        const float h = sHlo[clo];
+        uint4 w;
         if (PREC == kPrecFP32) {
-            bf[ct][0] = (float)((clo >> q) & 1);
-            bf[ct][1] = (float)((clo >> (4 + q)) & 1);
-            bf[ct][2] = h;  // h_lo of the lane's column, added with C before the products
-        } else {
-            if (q < 3) {
+            w.x = fbits((float)((clo >> q) & 1));
+            w.y = fbits((float)((clo >> (4 + q)) & 1));
+            w.z = fbits(h);  // h_lo of the lane's column, added with C before the products
+            w.w = 0u;
+        } else if (q < 3) {
+            uint32_t d4[4];
 #pragma unroll
-                for (int d = 0; d < 4; ++d)
-                    bw[ct][d] = ((clo >> (2 * d) & 1) ? 0x3F80u : 0u) |
-                                ((clo >> (2 * d + 1) & 1) ? 0x3F800000u : 0u);
-            } else {
-                const float h1 = trunc16(h);
-                const float r = h - h1;
-                const float h2 = trunc16(r);
-                const float h3 = r - h2;
-                bw[ct][0] = 0x3F803F80u;
-                bw[ct][1] = 0x3F80u | (fbits(h1) & 0xFFFF0000u);
-                bw[ct][2] = pack2(h2, h3);
-                bw[ct][3] = 0u;
-            }
+            for (int d = 0; d < 4; ++d)
+                d4[d] = ((clo >> (2 * d) & 1) ? 0x3F80u : 0u) |
+                        ((clo >> (2 * d + 1) & 1) ? 0x3F800000u : 0u);
+            w = make_uint4(d4[0], d4[1], d4[2], d4[3]);
+        } else {
+            const float h1 = trunc16(h);
+            const float r = h - h1;
+            const float h2 = trunc16(r);
+            const float h3 = r - h2;
+            w = make_uint4(0x3F803F80u, 0x3F80u | (fbits(h1) & 0xFFFF0000u), pack2(h2, h3), 0u);
         }
-    }
+        return w;
+    };
+    // in LDS, one table per block (the operands depend on the lane, not the
+    // wave): wave w builds column tiles 4 w .. 4 w + 3.  The near-tie sweep
+    // reads them there; the main sweep too, or from registers.
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sB[4 * wv + k][lane] = col_operand(4 * wv + k);
+    __syncthreads();
+    auto bop_lds = [&](int ct) -> uint4 { return sB[ct][lane]; };
+#if QA_BOUND_B_LDS
+    auto bop = bop_lds;
+#else
+    // in registers for the whole kernel
+    uint4 bw[16];
+#pragma unroll
+    for (int ct = 0; ct < 16; ++ct) bw[ct] = col_operand(ct);
+    auto bop = [&](int ct) -> uint4 { return bw[ct]; };
+#endif
     // constant chunk of an unused row: C = 1e30, so its states never win
     uint2 csent;
     {
@@ -651,34 +742,19 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                                     : make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
     }
 
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     int64_t nflag = 0, ngap = 0, nrows = 0, ncand = 0;
-    uint2 *ctab = sCt[wv];
     uint8_t *list = sList[wv];
     double *g64 = sG64[wv];
-    // lane i < 16 holds g0_i and n0_i, lanes 8..15 also s_{i-8}, lane 0 K,
-    // lane 1 mu (vector loads, one pixel ahead)
-    double gnext = 0.0;
-    int nnext = 0, knext = 0;
-    uint32_t fnext = 0, gsnext = 0;
-    float snext = 0.0f;
-    if (wave < P) {
-        gnext = pr[wave].g0[li];
-        nnext = pr[wave].n0[li];
-        snext = (li >= 8) ? pr[wave].s[li - 8] : (li == 1 ? pr[wave].mu : pr[wave].K);
-        if (PRUNED) fnext = pr[wave].free;
-        if (CLOSED) knext = pr[wave].k;
-        gsnext = pr[wave].guess;
-    }
+    float *ptab = sPt[wv];
+    float *win = sWin[wv];
     for (int64_t p = wave; p < P; p += nwaves) {
         const double gcur = gnext;
         const int ncur = nnext;
         const float scur = snext;
-        // free dots and raised count of the pixel (wave-uniform)
+        // free dots, raised count and guess of the pixel (wave-uniform)
         const uint32_t F = PRUNED ? __builtin_amdgcn_readfirstlane(fnext) : 0xFFFFu;
         const int kc = CLOSED ? __builtin_amdgcn_readfirstlane(knext) : 0;
-        const uint32_t gsb = __builtin_amdgcn_readfirstlane(gsnext);
+        const float egf = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(egnext)));
         if (p + nwaves < P) {
             gnext = pr[p + nwaves].g0[li];
             nnext = pr[p + nwaves].n0[li];
@@ -686,7 +762,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                               : (li == 1 ? pr[p + nwaves].mu : pr[p + nwaves].K);
             if (PRUNED) fnext = pr[p + nwaves].free;
             if (CLOSED) knext = pr[p + nwaves].k;
-            gsnext = pr[p + nwaves].guess;
+            egnext = pr[p + nwaves].eg;
         }
         // g0 beyond n is zero in the record.  Thresholded and closed sets: a
         // fixed dot's entry carries the penalty 2^100 (states raising it never
@@ -695,13 +771,12 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         const float gl = (float)gcur;
         const float glp = (PRUNED && !(F >> li & 1u)) ? 0x1p100f : gl;
         float g[16];
-        float gabs = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < 16; ++i)
             g[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(glp), i));
-            gabs += fabsf(PRUNED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gl), i))
-                                 : g[i]);
-        }
+        // sum |g_i| (every 16-lane row holds g0_0..15)
+        const float gabs = __int_as_float(__builtin_amdgcn_readfirstlane(
+            __float_as_int(row_sumf(fabsf(gl)))));
         const uint32_t Fhi = (F >> 8) & 0xFFu;
         const int nflo = __popc(F & 0xFFu);
         if (MODE == kPruned) ncand += 1ll << __popc(F & ((1u << n) - 1u));
@@ -715,12 +790,11 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         // ---- the bound terms of the setup: s = S (n0 - x_u)_hi and K ----
         if (lane < kMaxDot) g64[lane] = gcur;  // FP64 g of the near-tie re-score
         float sb[8];
-        float sabs = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < 8; ++i)
             sb[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scur), 8 + i));
-            sabs += fabsf(sb[i]);
-        }
+        const float sabs = __int_as_float(__builtin_amdgcn_readfirstlane(
+            __float_as_int(row_sumf(li >= 8 ? fabsf(scur) : 0.0f))));
         const float Kf = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scur), 0));
         const float muf = CLOSED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(scur), 1))
                                  : 0.0f;
@@ -736,64 +810,66 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         const float margin = 4.0f * delta + 0x1p-19f * (fabsf(Kf) + sabs + hsabs) +
                              (CLOSED ? 0x1p-19f * lsum * lsum * inv2g : 0.0f);
 
-        // ---- per lane: bound and constant chunk of high indices (q + 4 e) * 16 + row ----
-        float P1 = 0.0f, R1 = 0.0f, W1 = 0.0f;
+        // ---- per lane: the bounds of high indices (q + 4 e4) * 16 + row.
+        // Bits 0..3 of the index are the lane's row, bits 4 and 5 its quarter
+        // q, bits 6 and 7 the compile-time e4: the lane's part of b_hi^T s
+        // (and of w^T b_hi, popc) is summed once, e4's part added per index.
+        float Rb = Kf, Wb = 0.0f;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (mrow >> j & 1) {
-                P1 += g[8 + j];
-                R1 += sb[j];
-                W1 += wb[j];
+                Rb += sb[j];
+                Wb += wb[j];
             }
         }
+        if (q & 1) { Rb += sb[4]; Wb += wb[4]; }
+        if (q & 2) { Rb += sb[5]; Wb += wb[5]; }
+        const float s67 = sb[6] + sb[7], w67 = wb[6] + wb[7];
+        const int pcl = __popc((uint32_t)mrow) + __popc((uint32_t)q);
         float lb[4];
 #pragma unroll
         for (int e4 = 0; e4 < 4; ++e4) {
             const int rt = q + 4 * e4;
-            float P2 = 0.0f, R2 = 0.0f, W2 = 0.0f;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (rt >> j & 1) {
-                    P2 += g[12 + j];
-                    R2 += sb[4 + j];
-                    W2 += wb[4 + j];
-                }
-            }
             const int chi = rt * 16 + mrow;
-            float L = ((Kf + R1) + R2) + sHs[chi];
+            const float R = e4 == 0 ? Rb : Rb + (e4 == 1 ? sb[6] : (e4 == 2 ? sb[7] : s67));
+            float L = R + sHs[chi];
             bool ok = rt < nrt;
             if (PRUNED) ok = ok && !((uint32_t)chi & ~Fhi);  // raises a fixed high dot
             if (CLOSED) {
                 // m raised low dots: none of this high part's states is admissible
                 // unless 0 <= m <= free low dots
-                const int m = kc - __popc((uint32_t)chi);
-                const float dm = ((float)m - muf) - (W1 + W2);
+                const int m = kc - (pcl + __popc((uint32_t)e4));
+                const float W = e4 == 0 ? Wb : Wb + (e4 == 1 ? wb[6] : (e4 == 2 ? wb[7] : w67));
+                const float dm = ((float)m - muf) - W;
                 L += dm * dm * inv2g;
                 ok = ok && m >= 0 && m <= nflo;
             }
             lb[e4] = ok ? L : INFINITY;
-            const float C = (P1 + P2) + sH[chi];
-            if (PREC == kPrecFP32) {
-                ctab[chi] = make_uint2(fbits(C), 0u);
-            } else {
-                const float c1 = trunc16(C);
-                const float cr = C - c1;
-                const float c2 = trunc16(cr);
-                ctab[chi] = make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
-            }
+        }
+        // b_hi^T g_hi over the low four and the high four bits of the high
+        // index (lanes 0..15 and 16..31), for the constant chunks
+        // C(c_hi) = b_hi^T g_hi + 1/2 b_hi^T A_HH b_hi of the scored rows
+        if (lane < 32) {
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (li >> j & 1) v += (lane < 16) ? g[8 + j] : g[12 + j];
+            ptab[lane] = v;
         }
         // The rows to score.  The setup's guess (the rounding of x*; closed:
         // the k free dots with the largest fractional parts) is a state of
-        // the candidate set; its energy E_g (FP32 from the tables, error
-        // below delta / 5) bounds the approximate best from above (by
-        // E_g + 1.2 delta), so a high part whose bound exceeds
-        // E_g + margin + delta holds neither the argmin nor a near-tie state.
-        // When at most two tiles' worth of high parts pass that test they are
-        // the rows (most pixels); otherwise the row tile with the smallest
-        // bound is scored first and the high parts within the margin of its
-        // best (and under the first threshold) follow.
+        // the candidate set; its energy E_g (FP64 in the setup, rounded to
+        // FP32) bounds the approximate best from above (by E_g + 1.1 delta),
+        // so a high part whose bound exceeds E_g + margin + delta holds
+        // neither the argmin nor a near-tie state.  When at most two tiles'
+        // worth of high parts pass that test they are the rows (most pixels);
+        // otherwise the row tile with the smallest bound is scored first and
+        // the high parts within the margin of its best (and under the first
+        // threshold) follow.
         int rts = -1;
         int cnt = 0;  // scored rows (wave-uniform)
+        // appends the high indices whose bound is at most thr (except those
+        // of row tile skip_rt) to the list after position cnt
         auto list_rows = [&](float thr, int skip_rt) {
 #pragma unroll
             for (int e4 = 0; e4 < 4; ++e4) {
@@ -807,29 +883,14 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                 cnt += __popcll(m);
             }
         };
-        float thr_g = INFINITY;
-        bool by_guess = false;
-        {
-            const int chg = (int)(gsb >> 8), clg = (int)(gsb & 0xFFu);
-            const int rowg = chg & 15, rtg = chg >> 4;
-            float P1g = 0.0f, P2g = 0.0f;
+        const float thr_g = egf + margin + delta;
+        int ng = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (rowg >> j & 1) P1g += g[8 + j];
-                if (rtg >> j & 1) P2g += g[12 + j];
-            }
-            float Eg = ((P1g + P2g) + sH[chg]) + sHlo[clg];
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (clg >> i & 1) Eg += (g[i] + sT1[rowg][i]) + sT2[rtg][i];
-            thr_g = Eg + margin + delta;
-            int ng = 0;
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) ng += __popcll(__ballot(lb[e4] <= thr_g));
-            by_guess = ng <= 32;
-            if (by_guess) list_rows(thr_g, -1);
-        }
-        if (!by_guess) {
+        for (int e4 = 0; e4 < 4; ++e4) ng += __popcll(__ballot(lb[e4] <= thr_g));
+        const bool by_guess = ng <= 32;
+        if (by_guess) {
+            list_rows(thr_g, -1);
+        } else {
             float rlb[4];
 #pragma unroll
             for (int e4 = 0; e4 < 4; ++e4) rlb[e4] = row_min(lb[e4]);
@@ -845,7 +906,7 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
             if (lane < 16) list[lane] = (uint8_t)(rts * 16 + lane);
             cnt = 16;
         }
-        wave_sync();  // the constant chunks and the first rows
+        wave_sync();  // the row list and the b_hi^T g_hi tables
 
         // g_{2q}, g_{2q+1} (split-BF16 forms) or g_q, g_{4+q} (FP32) of this lane
         float ga = g[0], gb = g[1];
@@ -859,6 +920,8 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
         if (PREC == kPrecFP32) gb = (q == 0) ? g[4] : gb;
 
         auto ct_ok = [&](int ct) { return !PRUNED || !(((uint32_t)ct << 4) & ~F & 0xF0u); };
+        // C(c_hi) in FP32: the same sums as b_hi^T g_hi + table
+        auto cconst = [&](int chi) { return (ptab[chi & 15] + ptab[16 + (chi >> 4)]) + sH[chi]; };
         // closed: popcounts of this lane's four elements of tile t less that of
         // the column tile (rows 4q..4q+3, column bits mrow)
         auto elem_pc = [&](int t, int (&eq)[4]) {
@@ -878,31 +941,59 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
             }
             return d;
         };
-        // A operand of tile t: row r of the tile is high index list[16 t + r]
-        // (unused rows past cnt get the sentinel constant chunk)
-        auto build_rows = [&](int t, Pack8 &a, float (&af)[6]) {
+        // The A operand of tile t (row r of the tile is high index
+        // list[16 t + r]; unused rows past cnt get the sentinel constant
+        // chunk), in two steps so that the next tile's LDS reads are in
+        // flight while this tile is on the matrix core: fetch reads the
+        // tables, assemble forms the operand.
+        struct Rows {
+            float t1a, t1b, t2a, t2b;  // T1 and T2 entries of the lane's two dots
+            float c[4];                // X3/X2: c[0] = C of the lane's row; FP32: C of rows 4q + i
+            bool real;
+        };
+        auto fetch = [&](int t) -> Rows {
+            Rows r;
             const int idx = t * 16 + mrow;
-            const bool real = idx < cnt;
-            const int chi = real ? (int)list[idx] : 0;
+            r.real = idx < cnt;
+            const int chi = r.real ? (int)list[idx] : 0;
             const int row = chi & 15, rtt = chi >> 4;
-            const uint2 cw = real ? ctab[chi] : csent;
+            const int da = (PREC == kPrecFP32) ? q : 2 * q;
+            const int db = (PREC == kPrecFP32) ? 4 + q : 2 * q + 1;
+            r.t1a = sT1[row][da];
+            r.t1b = sT1[row][db];
+            r.t2a = sT2[rtt][da];
+            r.t2b = sT2[rtt][db];
             if (PREC == kPrecFP32) {
-                const float v0 = (ga + sT1[row][q]) + sT2[rtt][q];
-                const float v1 = (gb + sT1[row][4 + q]) + sT2[rtt][4 + q];
-                af[0] = v0;
-                af[1] = v1;
                 // C of the four output rows 4q..4q+3 of this lane: the
                 // accumulator starts at C(row) + h_lo(column), so two
                 // K = 4 products per tile suffice
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int ri = t * 16 + 4 * q + i;
-                    af[2 + i] = ri < cnt ? __uint_as_float(ctab[list[ri]].x) : 1e30f;
+                    r.c[i] = ri < cnt ? cconst(list[ri]) : 1e30f;
                 }
-                (void)cw;
             } else {
-                const float v0 = (ga + sT1[row][2 * q]) + sT2[rtt][2 * q];
-                const float v1 = (gb + sT1[row][2 * q + 1]) + sT2[rtt][2 * q + 1];
+                r.c[0] = r.real ? cconst(chi) : 0.0f;
+            }
+            return r;
+        };
+        auto assemble = [&](const Rows &r, Pack8 &a, float (&af)[6]) {
+            const float v0 = (ga + r.t1a) + r.t2a;
+            const float v1 = (gb + r.t1b) + r.t2b;
+            if (PREC == kPrecFP32) {
+                af[0] = v0;
+                af[1] = v1;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) af[2 + i] = r.c[i];
+            } else {
+                uint2 cw = csent;
+                if (r.real) {
+                    const float C = r.c[0];
+                    const float c1 = trunc16(C);
+                    const float cr = C - c1;
+                    const float c2 = trunc16(cr);
+                    cw = make_uint2(pack2(c1, c2), pack2(cr - c2, 1.0f));
+                }
                 uint32_t R0, R1, R2;
                 if (PREC == kPrecX3) {
                     const float a0 = trunc16(v0), b0 = trunc16(v1);
@@ -930,104 +1021,165 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                 a.u[3] = u23[1];
             }
         };
-        auto tile = [&](const Pack8 &a, const float (&af)[6], int ct) -> f32x4_t {
+        auto build_rows = [&](int t, Pack8 &a, float (&af)[6]) { assemble(fetch(t), a, af); };
+        auto tile = [&](const Pack8 &a, const float (&af)[6], int ct,
+                        bool from_lds = false) -> f32x4_t {
             f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            const uint4 bb = from_lds ? bop_lds(ct) : bop(ct);
             if (PREC == kPrecFP32) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i] = af[2 + i] + bf[ct][2];
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], bf[ct][0], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], bf[ct][1], acc, 0, 0, 0);
+                for (int i = 0; i < 4; ++i) acc[i] = af[2 + i] + __uint_as_float(bb.z);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[0], __uint_as_float(bb.x), acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[1], __uint_as_float(bb.y), acc, 0, 0, 0);
             } else {
                 Pack8 b;
-                b.u[0] = bw[ct][0]; b.u[1] = bw[ct][1]; b.u[2] = bw[ct][2]; b.u[3] = bw[ct][3];
+                b.u[0] = bb.x; b.u[1] = bb.y; b.u[2] = bb.z; b.u[3] = bb.w;
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
             }
             return acc;
         };
-        // per lane: smallest group minimum b1 (tile * 16 + ct in a1) and the
-        // second smallest group minimum b2
-        float b1 = INFINITY, b2 = INFINITY;
-        int a1 = 0;
-        auto track = [&](const f32x4_t &d, int code) {
-            const float m = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
-            const bool lt = m < b1;
-            b2 = fminf(b2, fmaxf(b1, m));
-            b1 = fminf(b1, m);
-            a1 = lt ? code : a1;
+        // the four column tiles 4 cg .. 4 cg + 3 of row tile (a, af): the
+        // lane's 16 elements (element 4 k + i: column tile 4 cg + k, output
+        // row 4 q + i); column tiles without a candidate read +inf
+        auto group = [&](const Pack8 &a, const float (&af)[6], const int (&eq)[4], auto cgc,
+                         f32x4_t (&d)[4]) {
+            constexpr int cg = decltype(cgc)::value;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int ct = 4 * cg + k;
+                if (ct_ok(ct)) d[k] = qualify(tile(a, af, ct), eq, ct);
+                else d[k] = f32x4_t{INFINITY, INFINITY, INFINITY, INFINITY};
+            }
         };
-        // software-pipelined: tile ct - 1 is tracked while tile ct is on the
-        // matrix core
-        auto score_tile = [&](int t) {
-            Pack8 a;
-            float af[6];
+        // Per lane: the three smallest group minima b1 <= b2 <= b3 and the
+        // group codes 4 t + cg of the first two (a1, a2), a group being the
+        // lane's 16 elements of four column tiles.  The A operand of tile 0 is
+        // kept for the winner's group.
+        float b1 = INFINITY, b2 = INFINITY, b3 = INFINITY;
+        int a1 = 0, a2 = 0;
+        uint32_t ac0 = 0, ac1 = 0, ac2 = 0, ac3 = 0;  // A operand of tile 0
+        float afc0 = 0.0f, afc1 = 0.0f, afc2 = 0.0f, afc3 = 0.0f, afc4 = 0.0f, afc5 = 0.0f;
+        auto score = [&](int t, const Pack8 &a, const float (&af)[6]) {
             int eq[4];
-            build_rows(t, a, af);
             elem_pc(t, eq);
-            if (PRUNED) {
-                // column tiles that raise a fixed dot of 4..7 hold no candidate
+            sfor<0, 4>([&](auto cgc) {
+                constexpr int cg = decltype(cgc)::value;
+                float m = INFINITY;
 #pragma unroll
-                for (int ct = 0; ct < 16; ++ct) {
+                for (int k = 0; k < 4; ++k) {
+                    const int ct = 4 * cg + k;
                     if (!ct_ok(ct)) continue;
-                    track(qualify(tile(a, af, ct), eq, ct), t * 16 + ct);
-                    __builtin_amdgcn_sched_barrier(0);
+                    const f32x4_t d = qualify(tile(a, af, ct), eq, ct);
+                    m = __builtin_fminf(m, __builtin_fminf(d[0], d[1]));
+                    m = __builtin_fminf(m, __builtin_fminf(d[2], d[3]));
                 }
-                return;
-            }
-            f32x4_t dp = qualify(tile(a, af, 0), eq, 0);
-#pragma unroll
-            for (int ct = 1; ct < 16; ++ct) {
-                const f32x4_t d = qualify(tile(a, af, ct), eq, ct);
-                track(dp, t * 16 + ct - 1);
-                dp = d;
+                const int code = 4 * t + cg;
+                b3 = __builtin_amdgcn_fmed3f(b2, b3, m);
+                a2 = (m < b1) ? a1 : ((m < b2) ? code : a2);
+                b2 = __builtin_amdgcn_fmed3f(b1, b2, m);
+                a1 = (m < b1) ? code : a1;
+                b1 = __builtin_fminf(b1, m);
+                // one group's products in flight at a time (their results
+                // are 16 registers)
                 __builtin_amdgcn_sched_barrier(0);
+            });
+        };
+        // tiles t0 .. t1 - 1, the next tile's tables read while this one is
+        // scored
+        auto score_range = [&](int t0, int t1) {
+            Rows rn = fetch(t0);
+            for (int t = t0; t < t1; ++t) {
+                Pack8 a;
+                float af[6];
+                assemble(rn, a, af);
+                if (t + 1 < t1) rn = fetch(t + 1);
+                if (t == 0) {
+                    ac0 = a.u[0]; ac1 = a.u[1]; ac2 = a.u[2]; ac3 = a.u[3];
+                    afc0 = af[0]; afc1 = af[1]; afc2 = af[2];
+                    afc3 = af[3]; afc4 = af[4]; afc5 = af[5];
+                }
+                score(t, a, af);
             }
-            track(dp, t * 16 + 15);
         };
         if (!by_guess) {
-            score_tile(0);
+            score_range(0, 1);
             // the other high indices whose bound admits a state within the
-            // margin of the best so far
+            // margin of the best so far, after the first row tile's 16
             list_rows(fminf(wave_min(b1) + margin, thr_g), rts);
             wave_sync();
         }
         const int ntiles = (cnt + 15) >> 4;
-        for (int t = by_guess ? 0 : 1; t < ntiles; ++t) score_tile(t);
+        score_range(by_guess ? 0 : 1, ntiles);
         nrows += cnt;
 
-        // ---- best over the wave, runner-up bound, winner's tile once more ----
-        const float wmin = wave_min(b1);
+        // ---- best over the wave (the smallest and second smallest group
+        // minima of all lanes in one reduction), runner-up bound, winner's
+        // group once more ----
+        float m1 = b1, m2 = INFINITY;
+        auto pair_step = [&](float o1, float o2) {
+            const float n2 = __builtin_fminf(__builtin_fmaxf(m1, o1), __builtin_fminf(m2, o2));
+            m1 = __builtin_fminf(m1, o1);
+            m2 = n2;
+        };
+        pair_step(dppf<kDppXor1>(m1), dppf<kDppXor1>(m2));
+        pair_step(dppf<kDppXor2>(m1), dppf<kDppXor2>(m2));
+        pair_step(dppf<kDppHalfMirror>(m1), dppf<kDppHalfMirror>(m2));
+        pair_step(dppf<kDppMirror>(m1), dppf<kDppMirror>(m2));
+        {
+            auto swap_pair = [&](auto swap) {
+                const auto s1 = swap(__float_as_uint(m1));
+                const auto s2 = swap(__float_as_uint(m2));
+                m1 = __uint_as_float(s1[0]);
+                m2 = __uint_as_float(s2[0]);
+                pair_step(__uint_as_float(s1[1]), __uint_as_float(s2[1]));
+            };
+            swap_pair([](uint32_t v) { return __builtin_amdgcn_permlane16_swap(v, v, false, false); });
+            swap_pair([](uint32_t v) { return __builtin_amdgcn_permlane32_swap(v, v, false, false); });
+        }
+        const float wmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m1)));
+        const float wsec = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m2)));
         const unsigned long long hit = __ballot(b1 == wmin);
         const int winner = __ffsll((long long)hit) - 1;
-        const float other = wave_min((lane == winner) ? b2 : b1);
+        const float other = fminf(wsec, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b2), winner)));
         const int aw = __builtin_amdgcn_readlane(a1, winner);
-        const int tw = aw >> 4, ctw = aw & 15;
-        float e1, e2;
-        int iw;
+        const int tw = aw >> 2, cgw = aw & 3;
         {
             Pack8 a;
             float af[6];
-            int eq[4];
-            build_rows(tw, a, af);
-            elem_pc(tw, eq);
-            f32x4_t d = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int ct = 0; ct < 16; ++ct)
-                if (ct == ctw) d = qualify(tile(a, af, ct), eq, ct);
-            float v1 = d[0], v2 = INFINITY;
-            int i1 = 0;
-#pragma unroll
-            for (int i = 1; i < 4; ++i) {
-                if (d[i] < v1) { v2 = v1; v1 = d[i]; i1 = i; }
-                else v2 = fminf(v2, d[i]);
+            if (tw == 0) {
+                a.u[0] = ac0; a.u[1] = ac1; a.u[2] = ac2; a.u[3] = ac3;
+                af[0] = afc0; af[1] = afc1; af[2] = afc2;
+                af[3] = afc3; af[4] = afc4; af[5] = afc5;
+            } else {
+                build_rows(tw, a, af);
             }
-            e1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v1), winner));
-            iw = __builtin_amdgcn_readlane(i1, winner);
-            e2 = fminf(other, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v2), winner)));
+            int eq[4];
+            elem_pc(tw, eq);
+            f32x4_t d[4] = {};
+            sfor<0, 4>([&](auto cgc) {
+                if (decltype(cgc)::value == cgw) group(a, af, eq, cgc, d);
+            });
+            if (lane == winner) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) win[4 * k + i] = d[k][i];
+            }
         }
+        wave_sync();
+        // lanes 0..15: element `lane` of the winner's group; the best, its
+        // first position and the second best by row reductions
+        const float x = lane < 16 ? win[lane] : INFINITY;
+        const float e1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_min(x))));
+        const int jw = __ffsll((long long)__ballot(lane < 16 && x == e1)) - 1;
+        const float x2 = lane == jw ? INFINITY : x;
+        const float v2 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(row_min(x2))));
+        const float e2 = fminf(other, v2);
         const bool tie = !(e2 - e1 > 2.0f * delta);
         if (!tie) {
             if (lane < n) {
-                const int row = 4 * (winner >> 4) + iw;
+                const int ctw = 4 * cgw + (jw >> 2);
+                const int row = 4 * (winner >> 4) + (jw & 3);
                 const uint32_t chi = list[tw * 16 + row];
                 const uint32_t clo = (uint32_t)(ctw * 16 + (winner & 15));
                 const uint32_t b = clo | (chi << 8);
@@ -1035,40 +1187,28 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
             }
             continue;
         }
-        // ---- near tie: the scored rows once more, each lane scores its own
-        // in-band states in FP64 (ties to the lexicographically smallest) ----
+        // ---- near tie: the exact argmin is one of the scored states whose
+        // approximate energy lies within 2 delta of the best (the band).  The
+        // groups that hold them are swept once more, the in-band states are
+        // gathered into a per-wave list (state codes clo | chi << 8), and the
+        // lanes score them in FP64, one state each, from the split tables
+        //   U(n0 + b) - U(n0) = h_lo(c_lo) + H_hi(c_hi) + b_hi^T g_hi
+        //                     + b_lo^T (g_lo + A_LH b_hi)
+        // keeping the smallest (ties to the lexicographically smallest
+        // state) ----
         ++nflag;
         const float thr = e1 + 2.0f * delta;
         double c1best = INFINITY, c2best = INFINITY;
         uint32_t cbest = 0;
-        for (int t = 0; t < ntiles; ++t) {
-            Pack8 a;
-            float af[6];
-            int eq[4];
-            build_rows(t, a, af);
-            elem_pc(t, eq);
-            uint32_t ib[2] = {0u, 0u};  // bit 4 ct + i: element i of tile ct
-#pragma unroll
-            for (int ct = 0; ct < 16; ++ct) {
-                if (!ct_ok(ct)) continue;
-                const f32x4_t d = qualify(tile(a, af, ct), eq, ct);
-                const float dm = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
-                if (dm <= thr) {
-                    uint32_t m4 = 0u;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) m4 |= (d[i] <= thr) ? 1u << i : 0u;
-                    ib[ct >> 3] |= m4 << (4 * (ct & 7));
-                }
-            }
-            uint64_t inband = ((uint64_t)ib[1] << 32) | ib[0];
-            while (inband) {
+        uint32_t *band = sBand[wv];
+        int nb = 0;  // states in the band list (wave-uniform)
+        auto flush = [&]() {
+            wave_sync();
+            for (int j = lane; j < nb; j += 64) {
                 // keep the FP64 tables in LDS (loads not hoisted into registers)
                 __asm__ volatile("" ::: "memory");
-                const int bit = __ffsll((long long)inband) - 1;
-                inband &= inband - 1;
-                const uint32_t clo = (uint32_t)((bit >> 2) * 16 + mrow);
-                const uint32_t chi = list[t * 16 + 4 * q + (bit & 3)];
-                const uint32_t c = clo | (chi << 8);
+                const uint32_t c = band[j];
+                const uint32_t clo = c & 0xFFu, chi = c >> 8;
                 const int row = chi & 15, rth = chi >> 4;
                 double e = sLd[clo] + sHd[chi];
 #pragma unroll
@@ -1082,7 +1222,70 @@ __global__ __launch_bounds__(256, QA_SCORER_WAVES) void k_score_bound(const Diag
                     c2best = fmin(c2best, e);
                 }
             }
+            wave_sync();
+            nb = 0;
+        };
+        // the in-band states of column tile ct of row tile (a, af) = tile t
+        // into the band list
+        auto gather = [&](int t, const Pack8 &a, const float (&af)[6], const int (&eq)[4], int ct) {
+            if (!ct_ok(ct)) return;
+            const f32x4_t d = qualify(tile(a, af, ct, true), eq, ct);
+            const float dm = fminf(fminf(d[0], d[1]), fminf(d[2], d[3]));
+            if (!__ballot(dm <= thr)) return;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool in = d[i] <= thr;
+                const unsigned long long m = __ballot(in);
+                if (in) {
+                    const uint32_t chi = list[t * 16 + 4 * q + i];
+                    band[nb + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0))] =
+                        (uint32_t)(ct * 16 + mrow) | (chi << 8);
+                }
+                nb += __popcll(m);
+                if (nb >= 64) flush();
+            }
+        };
+        auto operand = [&](int t, Pack8 &a, float (&af)[6]) {
+            if (t == 0) {
+                a.u[0] = ac0; a.u[1] = ac1; a.u[2] = ac2; a.u[3] = ac3;
+                af[0] = afc0; af[1] = afc1; af[2] = afc2;
+                af[3] = afc3; af[4] = afc4; af[5] = afc5;
+            } else {
+                build_rows(t, a, af);
+            }
+        };
+        if (!__ballot(b3 <= thr)) {
+            // no lane has a third group in the band: the in-band states lie
+            // in the groups a1 (where b1 <= thr) and a2 (where b2 <= thr) of
+            // the lanes; those groups (a mask over the codes 4 t + cg < 64)
+            // once more
+            uint64_t gm = (b1 <= thr ? 1ull << a1 : 0ull) | (b2 <= thr ? 1ull << a2 : 0ull);
+            gm = wave_or64(gm);
+            while (gm) {
+                const int gc = __ffsll((long long)gm) - 1;
+                gm &= gm - 1;
+                const int t = gc >> 2, cgs = gc & 3;
+                Pack8 a;
+                float af[6];
+                int eq[4];
+                operand(t, a, af);
+                elem_pc(t, eq);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) gather(t, a, af, eq, 4 * cgs + k);
+            }
+        } else {
+            // otherwise every scored row tile
+            for (int t = 0; t < ntiles; ++t) {
+                Pack8 a;
+                float af[6];
+                int eq[4];
+                operand(t, a, af);
+                elem_pc(t, eq);
+                for (int ct = 0; ct < 16; ++ct) gather(t, a, af, eq, ct);
+            }
         }
+        if (nb) flush();
         // (best, runner-up, state) over the wave: exchange with the partner
         // lanes of the row steps, then combine the swapped rows
         auto merge = [&](double ob1, double ob2, uint32_t oc1) {
