@@ -403,6 +403,24 @@ def run_extras(qa, W, torch, d, V, out, args, gpu):
                       "states_scored_per_pixel": round(st["scored"] / d.P, 1)}
         log("form %s: %s" % (key, forms[key]))
     res["forms_16dot"] = forms
+    # the same diagram described as a sweep of two virtual gates (qa_grid):
+    # the voltages are formed inside the kernels, none read from HBM
+    import ctypes as C
+    lib = qa.load()
+    gpb, gkeep = qa.make_problem(d.cdd, d.cgd, False, 0, 0.0, 1.0, args.precision)
+    grid, grkeep = qa.make_grid(d.sweep)
+    gstream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def grid_call():
+        st_ = lib.qa_ground_state_grid(C.byref(gpb), C.byref(grid), C.c_void_p(out.data_ptr()),
+                                       None, gstream)
+        if st_:
+            raise qa.QArrayError(st_, lib.qa_last_error().decode())
+    wall = timed_calls(grid_call, steps, 3, torch)
+    res["headline_as_sweep"] = {"pixels_per_s": round(d.P * steps / wall, 1),
+                                "ms_per_diagram": round(1e3 * wall / steps, 4),
+                                "what": "qa_ground_state_grid, %s" % args.precision}
+    log("headline as a sweep: %s" % res["headline_as_sweep"])
     # thresholded candidate sets of the same diagram (Sec. 3.2.2): the
     # headline form (sub-box per pixel on the matrix cores) and FP64 scoring
     pruned = {}
@@ -570,6 +588,19 @@ def run_extras(qa, W, torch, d, V, out, args, gpu):
                                "diagrams_per_s": round(args.batch_diagrams * nb / wall, 1),
                                "candidates": st["candidates"], "qp_pixels": st["qp_pixels"]}
         log("ragged batch: %s" % res["ragged_batch"])
+        # the same batch with every diagram passed as its sweep
+        # (qa_ground_state_batched_grid): no voltages in HBM
+        bs = qa.Batch(ds, sweeps=True)
+        bs.run()
+        torch.cuda.synchronize()
+        wall = timed_calls(lambda: bs.run(), nb, 1, torch)
+        hbm_s = sum(dg.P * 12 * dg.n_dot for dg in bs.diagrams)
+        res["ragged_batch_sweeps"] = {"ms_per_batch": round(1e3 * wall / nb, 3),
+                                      "pixels_per_s": round(bs.pixels * nb / wall, 1),
+                                      "hbm_bytes": hbm_s,
+                                      "hbm_GBps": round(hbm_s * nb / wall / 1e9, 1)}
+        log("ragged batch as sweeps: %s" % res["ragged_batch_sweeps"])
+        del bs
         # a seeded 64-diagram subset for the oracle comparison
         n_all, nbar_all = b.n.cpu().numpy(), b.nbar.cpu().numpy()
         gpu["batch"] = []

@@ -142,6 +142,33 @@ typedef struct {
 qa_status qa_ground_state(const qa_problem *prob, const double *V_dev, int64_t P,
                           int32_t *n_out_dev, qa_stats *stats, void *hip_stream);
 
+/* An affine two-dimensional sweep of the gate voltages: the raster scans of
+ * Sec. 5 (the gate-voltage composer's two-gate and do2d sweeps), and sweeps
+ * of two virtual gates (Fig. 1(b); Sec. 5.3, App. I: e1, e2 the columns of
+ * the virtual-gate matrix).  nx x ny pixels, pixel p = j * nx + i (the row is
+ * the second swept coordinate), with
+ *     a_i = linspace(a0, a1, nx)[i],  b_j = linspace(b0, b1, ny)[j],
+ *     V(i, j) = (v0 + a_i e1) + b_j e2,
+ * each operation rounded to FP64 on its own (no fused multiply-add) and a_i
+ * formed as numpy's linspace forms it (i * step + a0, the last point a1):
+ * the results are bitwise those of the explicit voltages numpy computes
+ * from the same description.  The voltages are formed inside the kernels
+ * and never stored.
+ *   v0, e1, e2 : host, n_gate doubles each, read before the call returns.
+ *   nx, ny     : >= 1, nx * ny < 2^31 (QA_E_SHAPE).  Non-finite values:
+ *                QA_E_RANGE; NULL pointers: QA_E_NULL. */
+typedef struct {
+    const double *v0, *e1, *e2;
+    double a0, a1;   /* first swept coordinate (columns of the raster) */
+    double b0, b1;   /* second swept coordinate (rows) */
+    int32_t nx, ny;
+} qa_grid;
+
+/* qa_ground_state over a sweep: P = nx * ny pixels, n_out_dev P x N int32
+ * (row-major in p).  Launches directly (never as a graph replay). */
+qa_status qa_ground_state_grid(const qa_problem *prob, const qa_grid *grid, int32_t *n_out_dev,
+                               qa_stats *stats, void *hip_stream);
+
 /* qa_ground_state for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same problem, inputs, output and result as qa_ground_state,
@@ -201,6 +228,20 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
                                   double *grad_cdd_dev, double *grad_cgd_dev,
                                   double *grad_V_dev, void *hip_stream);
 
+/* qa_soft_charge over a sweep (qa_grid): P = nx * ny pixels; nbar_out_dev
+ * P x N FP64 and saved_dev qa_saved_bytes(P, N) as for qa_soft_charge. */
+qa_status qa_soft_charge_grid(const qa_problem *prob, const qa_grid *grid, double *nbar_out_dev,
+                              void *saved_dev, qa_stats *stats, void *hip_stream);
+
+/* qa_soft_charge_backward over a sweep: the saved buffer of a
+ * qa_soft_charge_grid call with the same problem and sweep.  grad_V_dev
+ * (P x G FP64, or NULL) receives dL/dV of every pixel's voltages (the
+ * sweep's derivatives follow from them by the chain rule). */
+qa_status qa_soft_charge_backward_grid(const qa_problem *prob, const qa_grid *grid,
+                                       const double *grad_nbar_dev, const void *saved_dev,
+                                       double *grad_cdd_dev, double *grad_cgd_dev,
+                                       double *grad_V_dev, void *hip_stream);
+
 /* Bytes of the saved buffer for P pixels of an N-dot problem. */
 size_t qa_saved_bytes(int64_t P, int32_t n_dot);
 
@@ -229,6 +270,16 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
                                   const int64_t *v_offsets, const int64_t *pix_counts,
                                   const int64_t *out_offsets, int32_t *n_out_dev,
                                   double *nbar_out_dev, qa_stats *stats, void *hip_stream);
+
+/* qa_ground_state_batched over sweeps: diagram d is the sweep grids[d]
+ * (P_d = nx * ny pixels, validated as for qa_ground_state_grid); its
+ * outputs are the P_d x N_d block at element out_offsets[d], as for the
+ * explicit-voltage form.  The sweeps are uploaded with the matrices and the
+ * voltages are formed inside the kernel. */
+qa_status qa_ground_state_batched_grid(const qa_problem *probs, int32_t n_diag,
+                                       const qa_grid *grids, const int64_t *out_offsets,
+                                       int32_t *n_out_dev, double *nbar_out_dev, qa_stats *stats,
+                                       void *hip_stream);
 
 /* Stage timing (diagnostics).  While enabled, every ground-state call on a
  * stream records HIP events on that stream around its stages:

@@ -227,6 +227,39 @@ qa_status validate(const qa_problem *pb, bool need_kT)
     return QA_OK;
 }
 
+// Validate a sweep descriptor for a problem with n_gate gates and fill the
+// device form; P receives nx * ny.
+qa_status fill_grid(const qa_grid *gd, int n_gate, VGrid *vg, int64_t *P)
+{
+    if (!gd) return fail(QA_E_NULL, "grid is NULL");
+    if (!gd->v0 || !gd->e1 || !gd->e2) return fail(QA_E_NULL, "grid v0, e1 or e2 is NULL");
+    if (gd->nx < 1 || gd->ny < 1 || (int64_t)gd->nx * gd->ny > INT32_MAX)
+        return fail(QA_E_SHAPE, "grid nx=%d, ny=%d: each >= 1, nx * ny < 2^31", gd->nx, gd->ny);
+    const double ends[4] = {gd->a0, gd->a1, gd->b0, gd->b1};
+    for (double e : ends)
+        if (!std::isfinite(e)) return fail(QA_E_RANGE, "grid range is not finite");
+    std::memset(vg, 0, sizeof *vg);
+    for (int k = 0; k < n_gate; ++k) {
+        if (!std::isfinite(gd->v0[k]) || !std::isfinite(gd->e1[k]) || !std::isfinite(gd->e2[k]))
+            return fail(QA_E_RANGE, "grid vector entry %d is not finite", k);
+        vg->v0[k] = gd->v0[k];
+        vg->e1[k] = gd->e1[k];
+        vg->e2[k] = gd->e2[k];
+    }
+    // linspace: the step (stop - start) / (num - 1); a single point is start
+    vg->a0 = gd->a0;
+    vg->a1 = gd->a1;
+    vg->da = gd->nx > 1 ? (gd->a1 - gd->a0) / (double)(gd->nx - 1) : 0.0;
+    vg->b0 = gd->b0;
+    vg->b1 = gd->b1;
+    vg->db = gd->ny > 1 ? (gd->b1 - gd->b0) / (double)(gd->ny - 1) : 0.0;
+    vg->nx = gd->nx;
+    vg->ny = gd->ny;
+    vg->on = 1;
+    *P = (int64_t)gd->nx * gd->ny;
+    return QA_OK;
+}
+
 void fill_diag(const qa_problem *pb, DiagRec *h)
 {
     std::memset(h, 0, sizeof(DiagRec));
@@ -316,11 +349,13 @@ hipError_t launch_scorer(const DiagRec *dr, const PixRec *pr, int64_t *counters,
 // bstats 4 * setup_blocks(P, n_dot) counts.  ev: optional stage events.
 qa_status enqueue_path(DiagRec *dr, PixRec *pr, int64_t *counters, int32_t *bstats, hipStream_t s,
                        const qa_problem *pb, const double *V, int64_t P, int32_t *n_out,
-                       double *nbar, SavedRec *saved, std::array<hipEvent_t, 4> *ev)
+                       double *nbar, SavedRec *saved, std::array<hipEvent_t, 4> *ev,
+                       const VGrid *sweep = nullptr)
 {
     const bool closed = pb->mode == QA_CLOSED;
     if (ev) QA_HIP(hipEventRecord((*ev)[0], s));
-    QA_HIP(launch_setup(dr, V, P, pr, counters, bstats, pb->n_dot, closed, s));
+    QA_HIP(launch_setup(dr, V, P, pr, counters, bstats, pb->n_dot, closed, s, nullptr, nullptr,
+                        sweep));
     if (ev) QA_HIP(hipEventRecord((*ev)[1], s));
     if (nbar)
         QA_HIP(launch_soft_fwd(dr, pr, P, nbar, saved, counters, pb->n_dot, s));
@@ -334,25 +369,27 @@ qa_status enqueue_path(DiagRec *dr, PixRec *pr, int64_t *counters, int32_t *bsta
 // the same on a workspace's buffers
 qa_status enqueue_single(Workspace *w, hipStream_t s, const qa_problem *pb, const double *V,
                          int64_t P, int32_t *n_out, double *nbar, SavedRec *saved,
-                         std::array<hipEvent_t, 4> *ev)
+                         std::array<hipEvent_t, 4> *ev, const VGrid *sweep = nullptr)
 {
     qa_status st = enqueue_path(w->dr, w->pr, w->counters, w->bstats, s, pb, V, P, n_out, nbar,
-                                saved, ev);
+                                saved, ev, sweep);
     if (!st) w->dr_derived = true;
     return st;
 }
 
-// Run a single-diagram call: with stage timing on, direct launches with
-// events; otherwise replay (or capture) the graph of this launch shape.
+// Run a single-diagram call: with stage timing on, or with a sweep (whose
+// values travel in the kernel arguments), direct launches; otherwise replay
+// (or capture) the graph of this launch shape.
 qa_status run_single(Workspace *w, const qa_problem *pb, const double *V, int64_t P,
-                     int32_t *n_out, double *nbar, SavedRec *saved)
+                     int32_t *n_out, double *nbar, SavedRec *saved, const VGrid *sweep = nullptr)
 {
     qa_status st;
     if ((st = grow_single(w, P))) return st;
     if ((st = upload_diag(w, pb))) return st;
     w->bstats_used = setup_blocks(P, pb->n_dot);
     std::array<hipEvent_t, 4> *ev = timing_slot(w);
-    if (ev || !g_graphs) return enqueue_single(w, w->stream, pb, V, P, n_out, nbar, saved, ev);
+    if (ev || !g_graphs || sweep)
+        return enqueue_single(w, w->stream, pb, V, P, n_out, nbar, saved, ev, sweep);
     const int path = nbar ? 2 : (use_matrix_cores(pb) ? 10 + 3 * pb->precision + scorer_mode(pb) : 1);
     std::vector<int64_t> key = {pb->n_dot, pb->mode, path, pb->flags, P, (int64_t)(uintptr_t)V,
                                 (int64_t)(uintptr_t)n_out, (int64_t)(uintptr_t)nbar,
@@ -414,6 +451,45 @@ qa_status read_stats(Workspace *w, qa_stats *stats)
     // only the bound-ordered search skips candidates; the other scorers
     // compute every energy of the candidate set
     stats->scored = c[C_SCORED] ? c[C_SCORED] : c[C_CANDIDATES];
+    return QA_OK;
+}
+
+// The adjoint's device work (validated problem; voltages V or the sweep vg)
+qa_status backward(const qa_problem *prob, const double *V_dev, const VGrid *vg, int64_t P,
+                   const double *grad_nbar_dev, const void *saved_dev, double *grad_cdd_dev,
+                   double *grad_cgd_dev, double *grad_V_dev, void *hip_stream)
+{
+    qa_status st;
+    if (prob->n_dot > 12)
+        return fail(QA_E_UNSUPPORTED, "the adjoint is built for n_dot <= 12 (got %d)", prob->n_dot);
+    if (!grad_cdd_dev || !grad_cgd_dev) return fail(QA_E_NULL, "gradient output is NULL");
+    if (P > 0 && (!grad_nbar_dev || !saved_dev))
+        return fail(QA_E_NULL, "grad_nbar_dev or saved_dev is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    DiagRec *dr0 = w->dr;
+    if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
+    if (w->dr != dr0) w->dr_inputs.clear();
+    const int64_t nacc = (int64_t)kBwdReplicas * kBwdAccWords;
+    double *acc0 = w->acc;
+    if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
+    if (w->acc != acc0) w->acc_zero = false;
+    if ((st = upload_diag(w, prob))) return st;
+    // the prologue (A, C_dd 1, tables) only when the record does not already
+    // hold it for these inputs (the usual case after the forward call);
+    // it also clears the accumulators when they are not known to be zero
+    const int64_t nzero = w->acc_zero ? 0 : nacc;
+    if (!w->dr_derived) {
+        QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream, nzero ? w->acc : nullptr, nzero));
+        w->dr_derived = true;
+    } else if (nzero) {
+        QA_HIP(launch_zero_i64(reinterpret_cast<int64_t *>(w->acc), (int)nzero, w->stream));
+    }
+    w->acc_zero = false;  // until the final kernel below is enqueued
+    QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, w->acc,
+                           grad_V_dev, prob->n_dot, w->stream, vg));
+    QA_HIP(launch_soft_bwd_final(w->dr, w->acc, grad_cdd_dev, grad_cgd_dev, w->stream));
+    w->acc_zero = true;
     return QA_OK;
 }
 
@@ -545,6 +621,22 @@ qa_status qa_ground_state_noalloc(const qa_problem *prob, const double *V_dev, i
                         nullptr);
 }
 
+qa_status qa_ground_state_grid(const qa_problem *prob, const qa_grid *grid, int32_t *n_out_dev,
+                               qa_stats *stats, void *hip_stream)
+{
+    clear_error();
+    qa_status st = validate(prob, false);
+    if (st) return st;
+    VGrid vg;
+    int64_t P = 0;
+    if ((st = fill_grid(grid, prob->n_gate, &vg, &P))) return st;
+    if (!n_out_dev) return fail(QA_E_NULL, "n_out_dev is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    if ((st = run_single(w, prob, nullptr, P, n_out_dev, nullptr, nullptr, &vg))) return st;
+    return read_stats(w, stats);
+}
+
 qa_status qa_continuous_min(const qa_problem *prob, const double *V_dev, int64_t P,
                             double *x_out_dev, int32_t *flags_out_dev, qa_stats *stats,
                             void *hip_stream)
@@ -593,6 +685,23 @@ qa_status qa_soft_charge(const qa_problem *prob, const double *V_dev, int64_t P,
     return read_stats(w, stats);
 }
 
+qa_status qa_soft_charge_grid(const qa_problem *prob, const qa_grid *grid, double *nbar_out_dev,
+                              void *saved_dev, qa_stats *stats, void *hip_stream)
+{
+    clear_error();
+    qa_status st = validate(prob, true);
+    if (st) return st;
+    VGrid vg;
+    int64_t P = 0;
+    if ((st = fill_grid(grid, prob->n_gate, &vg, &P))) return st;
+    if (!nbar_out_dev) return fail(QA_E_NULL, "nbar_out_dev is NULL");
+    Workspace *w;
+    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
+    if ((st = run_single(w, prob, nullptr, P, nullptr, nbar_out_dev, (SavedRec *)saved_dev, &vg)))
+        return st;
+    return read_stats(w, stats);
+}
+
 qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, int64_t P,
                                   const double *grad_nbar_dev, const void *saved_dev,
                                   double *grad_cdd_dev, double *grad_cgd_dev, double *grad_V_dev,
@@ -601,38 +710,25 @@ qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, i
     clear_error();
     qa_status st = validate(prob, true);
     if (st) return st;
-    if (prob->n_dot > 12)
-        return fail(QA_E_UNSUPPORTED, "the adjoint is built for n_dot <= 12 (got %d)", prob->n_dot);
     if (P < 0 || P > INT32_MAX) return fail(QA_E_SHAPE, "P=%lld outside [0, 2^31)", (long long)P);
-    if (!grad_cdd_dev || !grad_cgd_dev) return fail(QA_E_NULL, "gradient output is NULL");
-    if (P > 0 && (!V_dev || !grad_nbar_dev || !saved_dev))
-        return fail(QA_E_NULL, "V_dev, grad_nbar_dev or saved_dev is NULL");
-    Workspace *w;
-    if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
-    DiagRec *dr0 = w->dr;
-    if ((st = grow(w, w->dr, w->dr_cap, 1))) return st;
-    if (w->dr != dr0) w->dr_inputs.clear();
-    const int64_t nacc = (int64_t)kBwdReplicas * kBwdAccWords;
-    double *acc0 = w->acc;
-    if ((st = grow(w, w->acc, w->acc_cap, nacc))) return st;
-    if (w->acc != acc0) w->acc_zero = false;
-    if ((st = upload_diag(w, prob))) return st;
-    // the prologue (A, C_dd 1, tables) only when the record does not already
-    // hold it for these inputs (the usual case after the forward call);
-    // it also clears the accumulators when they are not known to be zero
-    const int64_t nzero = w->acc_zero ? 0 : nacc;
-    if (!w->dr_derived) {
-        QA_HIP(launch_prep(w->dr, 1, nullptr, w->stream, nzero ? w->acc : nullptr, nzero));
-        w->dr_derived = true;
-    } else if (nzero) {
-        QA_HIP(launch_zero_i64(reinterpret_cast<int64_t *>(w->acc), (int)nzero, w->stream));
-    }
-    w->acc_zero = false;  // until the final kernel below is enqueued
-    QA_HIP(launch_soft_bwd(w->dr, V_dev, P, grad_nbar_dev, (const SavedRec *)saved_dev, w->acc,
-                           grad_V_dev, prob->n_dot, w->stream));
-    QA_HIP(launch_soft_bwd_final(w->dr, w->acc, grad_cdd_dev, grad_cgd_dev, w->stream));
-    w->acc_zero = true;
-    return QA_OK;
+    if (P > 0 && !V_dev) return fail(QA_E_NULL, "V_dev is NULL");
+    return backward(prob, V_dev, nullptr, P, grad_nbar_dev, saved_dev, grad_cdd_dev, grad_cgd_dev,
+                    grad_V_dev, hip_stream);
+}
+
+qa_status qa_soft_charge_backward_grid(const qa_problem *prob, const qa_grid *grid,
+                                       const double *grad_nbar_dev, const void *saved_dev,
+                                       double *grad_cdd_dev, double *grad_cgd_dev,
+                                       double *grad_V_dev, void *hip_stream)
+{
+    clear_error();
+    qa_status st = validate(prob, true);
+    if (st) return st;
+    VGrid vg;
+    int64_t P = 0;
+    if ((st = fill_grid(grid, prob->n_gate, &vg, &P))) return st;
+    return backward(prob, nullptr, &vg, P, grad_nbar_dev, saved_dev, grad_cdd_dev, grad_cgd_dev,
+                    grad_V_dev, hip_stream);
 }
 
 }  // extern "C"
@@ -647,9 +743,11 @@ struct BatchPlan {
     int max_dot = 0;
 };
 
+// (grids: NULL, or one sweep per diagram, validated; then v_offsets and
+// pix_counts are unused)
 void plan_batch(const qa_problem *probs, int32_t n_diag, const int64_t *v_offsets,
-                const int64_t *pix_counts, const int64_t *out_offsets, bool by_size,
-                BatchPlan &plan)
+                const int64_t *pix_counts, const qa_grid *grids, const int64_t *out_offsets,
+                bool by_size, BatchPlan &plan)
 {
     std::vector<int> order(n_diag);
     for (int d = 0; d < n_diag; ++d) order[d] = d;
@@ -673,13 +771,31 @@ void plan_batch(const qa_problem *probs, int32_t n_diag, const int64_t *v_offset
         h.nhat = pb.mode == QA_CLOSED ? pb.n_charge : 0;
         h.kT = pb.kT;
         h.t = pb.threshold;
-        h.v_off = v_offsets[d];
         h.out_off = out_offsets[d];
-        h.P = pix_counts[d];
         h.mat_off = (int64_t)plan.mats.size();
         h.tile0 = plan.tiles;
         plan.mats.insert(plan.mats.end(), pb.cdd, pb.cdd + pb.n_dot * pb.n_dot);
         plan.mats.insert(plan.mats.end(), pb.cgd, pb.cgd + pb.n_dot * pb.n_gate);
+        if (grids) {
+            const qa_grid &gd = grids[d];
+            h.v_off = 0;
+            h.nx = gd.nx;
+            h.ny = gd.ny;
+            h.P = (int64_t)gd.nx * gd.ny;
+            h.grid_off = (int64_t)plan.mats.size();
+            plan.mats.insert(plan.mats.end(), gd.v0, gd.v0 + pb.n_gate);
+            plan.mats.insert(plan.mats.end(), gd.e1, gd.e1 + pb.n_gate);
+            plan.mats.insert(plan.mats.end(), gd.e2, gd.e2 + pb.n_gate);
+            const double da = gd.nx > 1 ? (gd.a1 - gd.a0) / (double)(gd.nx - 1) : 0.0;
+            const double db = gd.ny > 1 ? (gd.b1 - gd.b0) / (double)(gd.ny - 1) : 0.0;
+            const double sc[6] = {gd.a0, da, gd.a1, gd.b0, db, gd.b1};
+            plan.mats.insert(plan.mats.end(), sc, sc + 6);
+        } else {
+            h.v_off = v_offsets[d];
+            h.P = pix_counts[d];
+            h.grid_off = 0;
+            h.nx = h.ny = 0;
+        }
         plan.tiles += (h.P + 63) / 64;
         plan.max_dot = std::max(plan.max_dot, pb.n_dot);
     }
@@ -736,8 +852,8 @@ qa_status enqueue_batch(Workspace *w, hipStream_t s, int32_t n_diag, const Batch
 {
     QA_HIP(launch_zero_i64(w->counters, kCounterWords, s));
     QA_HIP(launch_prep_batch(w->bhdr, w->bmats, w->brecs, n_diag, s));
-    QA_HIP(launch_batch(w->bhdr, w->brecs, n_diag, plan.tiles, V, n_out, nbar, w->counters,
-                        plan.max_dot, blocks, s));
+    QA_HIP(launch_batch(w->bhdr, w->brecs, w->bmats, n_diag, plan.tiles, V, n_out, nbar,
+                        w->counters, plan.max_dot, blocks, s));
     return QA_OK;
 }
 
@@ -745,33 +861,46 @@ qa_status enqueue_batch(Workspace *w, hipStream_t s, int32_t n_diag, const Batch
 
 extern "C" {
 
-qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
-                                  const int64_t *v_offsets, const int64_t *pix_counts,
-                                  const int64_t *out_offsets, int32_t *n_out_dev,
-                                  double *nbar_out_dev, qa_stats *stats, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// a batch of explicit-voltage diagrams (grids NULL) or of sweeps
+qa_status batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
+                  const int64_t *v_offsets, const int64_t *pix_counts, const qa_grid *grids,
+                  const int64_t *out_offsets, int32_t *n_out_dev, double *nbar_out_dev,
+                  qa_stats *stats, void *hip_stream)
 {
-    clear_error();
     read_env();
     if (n_diag < 0) return fail(QA_E_SHAPE, "n_diag=%d is negative", n_diag);
     if (n_diag == 0) {
         if (stats) std::memset(stats, 0, sizeof *stats);
         return QA_OK;
     }
-    if (!probs || !v_offsets || !pix_counts || !out_offsets)
+    if (!probs || !out_offsets || (!grids && (!v_offsets || !pix_counts)))
         return fail(QA_E_NULL, "probs or an offset array is NULL");
     int64_t total = 0;
     for (int d = 0; d < n_diag; ++d) {
         qa_status st = validate(&probs[d], false);
         if (st) return fail(st, "diagram %d: %s", d, g_err);
-        if (pix_counts[d] < 0 || v_offsets[d] < 0 || out_offsets[d] < 0)
-            return fail(QA_E_SHAPE, "diagram %d: negative pixel count or offset", d);
-        total += pix_counts[d];
+        int64_t P = 0;
+        if (grids) {
+            VGrid vg;
+            if ((st = fill_grid(&grids[d], probs[d].n_gate, &vg, &P)))
+                return fail(st, "diagram %d: %s", d, g_err);
+        } else {
+            if (pix_counts[d] < 0 || v_offsets[d] < 0)
+                return fail(QA_E_SHAPE, "diagram %d: negative pixel count or offset", d);
+            P = pix_counts[d];
+        }
+        if (out_offsets[d] < 0) return fail(QA_E_SHAPE, "diagram %d: negative offset", d);
+        total += P;
     }
     if (total == 0) {
         if (stats) std::memset(stats, 0, sizeof *stats);
         return QA_OK;
     }
-    if (!V_dev || !n_out_dev) return fail(QA_E_NULL, "V_dev or n_out_dev is NULL");
+    if ((!grids && !V_dev) || !n_out_dev) return fail(QA_E_NULL, "V_dev or n_out_dev is NULL");
     Workspace *w;
     qa_status st;
     if ((st = get_ws((hipStream_t)hip_stream, &w))) return st;
@@ -783,7 +912,8 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
         n_soft += probs[d].kT > 0.0;
     }
     w->bstats_used = 0;  // the batched kernels count into the counter slots only
-    std::vector<int64_t> sig = {n_diag, total, max_dot, n_soft > 0 && nbar_out_dev != nullptr};
+    std::vector<int64_t> sig = {n_diag, total, max_dot, n_soft > 0 && nbar_out_dev != nullptr,
+                                grids != nullptr};
     BatchPlan plan;
     auto it = g_tune.find(sig);
     if (it == g_tune.end() && g_autotune) {
@@ -799,7 +929,8 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
         BatchTune best{cus * 4, true};
         float best_ms = 1e30f;
         for (int by_size = 0; by_size < 2; ++by_size) {
-            plan_batch(probs, n_diag, v_offsets, pix_counts, out_offsets, by_size != 0, plan);
+            plan_batch(probs, n_diag, v_offsets, pix_counts, grids, out_offsets, by_size != 0,
+                       plan);
             if ((st = upload_plan(w, plan, n_diag))) return st;
             for (int mult : {2, 4, 8, 16}) {
                 const int blocks = cus * mult;
@@ -819,7 +950,7 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
         it = g_tune.emplace(sig, best).first;
     }
     const BatchTune tune = (it != g_tune.end()) ? it->second : BatchTune{1024, true};
-    plan_batch(probs, n_diag, v_offsets, pix_counts, out_offsets, tune.by_size, plan);
+    plan_batch(probs, n_diag, v_offsets, pix_counts, grids, out_offsets, tune.by_size, plan);
     if ((st = upload_plan(w, plan, n_diag))) return st;
 
     if (!g_graphs) {
@@ -859,6 +990,31 @@ qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const
     }
     QA_HIP(hipGraphLaunch(w->graph, w->stream));
     return read_stats(w, stats);
+}
+
+}  // namespace
+
+extern "C" {
+
+qa_status qa_ground_state_batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
+                                  const int64_t *v_offsets, const int64_t *pix_counts,
+                                  const int64_t *out_offsets, int32_t *n_out_dev,
+                                  double *nbar_out_dev, qa_stats *stats, void *hip_stream)
+{
+    clear_error();
+    return batched(probs, n_diag, V_dev, v_offsets, pix_counts, nullptr, out_offsets, n_out_dev,
+                   nbar_out_dev, stats, hip_stream);
+}
+
+qa_status qa_ground_state_batched_grid(const qa_problem *probs, int32_t n_diag,
+                                       const qa_grid *grids, const int64_t *out_offsets,
+                                       int32_t *n_out_dev, double *nbar_out_dev, qa_stats *stats,
+                                       void *hip_stream)
+{
+    clear_error();
+    if (n_diag > 0 && !grids) return fail(QA_E_NULL, "grids is NULL");
+    return batched(probs, n_diag, nullptr, nullptr, nullptr, grids, out_offsets, n_out_dev,
+                   nbar_out_dev, stats, hip_stream);
 }
 
 void qa_timing_enable(int on) { g_timing = on != 0; }

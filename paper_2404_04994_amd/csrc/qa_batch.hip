@@ -168,11 +168,12 @@ __device__ __forceinline__ int64_t dense_small(const double *__restrict__ sh,
 }
 
 // one pixel, lane-sequential: returns the number of candidates scored
-template <int NM>
+// (volt(j): the pixel's voltage of gate j)
+template <int NM, typename Volt>
 __device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
                                                const double *__restrict__ A,
                                                const double *__restrict__ hs, bool closed,
-                                               const double *__restrict__ Vp,
+                                               Volt &&volt,
                                                int32_t *__restrict__ nout,
                                                double *__restrict__ nbout, int &qp, int &fail,
                                                int &dbl, int &gap)
@@ -183,7 +184,7 @@ __device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
     for (int i = 0; i < NM; ++i) {
         double s = 0.0;
         if (i < n)
-            for (int j = 0; j < g; ++j) s += dr->Cgd[i * kMaxGate + j] * Vp[j];
+            for (int j = 0; j < g; ++j) s += dr->Cgd[i * kMaxGate + j] * volt(j);
         xu[i] = s;
     }
     // analytic minimum first (Sec. 3.1.1), the QP only when it is negative
@@ -296,7 +297,8 @@ __device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
 
 template <int NM>
 __global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
-                                              const DiagRec *__restrict__ recs, int n_diag,
+                                              const DiagRec *__restrict__ recs,
+                                              const double *__restrict__ mats, int n_diag,
                                               int64_t tiles, const double *__restrict__ V,
                                               int32_t *__restrict__ n_out,
                                               double *__restrict__ nbar,
@@ -345,7 +347,19 @@ __global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
         const int64_t p = (item - h.tile0) * 64 + lane;
         if (p < h.P) {
             int qp = 0, fail = 0, dbl = 0, gap = 0;
-            ncand += batch_pixel<NM>(dr, sA, sh, h.closed != 0, V + h.v_off + p * h.g,
+            // the voltages: read, or formed from the diagram's sweep
+            const double *Vp = V + h.v_off + p * h.g;
+            const double *gv = mats + h.grid_off;
+            double va = 0.0, vb = 0.0;
+            if (h.nx > 0) {
+                const double *sc = gv + 3 * h.g;  // a0, da, a1, b0, db, b1
+                va = lin_point(p % h.nx, h.nx, sc[0], sc[1], sc[2]);
+                vb = lin_point(p / h.nx, h.ny, sc[3], sc[4], sc[5]);
+            }
+            auto volt = [&](int j) {
+                return h.nx > 0 ? sweep_volt(gv[j], gv[h.g + j], gv[2 * h.g + j], va, vb) : Vp[j];
+            };
+            ncand += batch_pixel<NM>(dr, sA, sh, h.closed != 0, volt,
                                      n_out + h.out_off + p * h.n,
                                      nbar ? nbar + h.out_off + p * h.n : nullptr, qp, fail, dbl,
                                      gap);
@@ -374,19 +388,19 @@ __global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
     }
 }
 
-hipError_t launch_batch(const BatchHdr *hdr, const DiagRec *recs, int n_diag, int64_t tiles,
-                        const double *V, int32_t *n_out, double *nbar, int64_t *counters,
-                        int max_dot, int blocks, hipStream_t s)
+hipError_t launch_batch(const BatchHdr *hdr, const DiagRec *recs, const double *mats, int n_diag,
+                        int64_t tiles, const double *V, int32_t *n_out, double *nbar,
+                        int64_t *counters, int max_dot, int blocks, hipStream_t s)
 {
     if (blocks < 1) blocks = 1;
     if (max_dot <= 4)
-        hipLaunchKernelGGL(k_batch<4>, dim3(blocks), dim3(64), 0, s, hdr, recs, n_diag, tiles, V,
+        hipLaunchKernelGGL(k_batch<4>, dim3(blocks), dim3(64), 0, s, hdr, recs, mats, n_diag, tiles, V,
                            n_out, nbar, counters);
     else if (max_dot <= 8)
-        hipLaunchKernelGGL(k_batch<8>, dim3(blocks), dim3(64), 0, s, hdr, recs, n_diag, tiles, V,
+        hipLaunchKernelGGL(k_batch<8>, dim3(blocks), dim3(64), 0, s, hdr, recs, mats, n_diag, tiles, V,
                            n_out, nbar, counters);
     else
-        hipLaunchKernelGGL(k_batch<16>, dim3(blocks), dim3(64), 0, s, hdr, recs, n_diag, tiles, V,
+        hipLaunchKernelGGL(k_batch<16>, dim3(blocks), dim3(64), 0, s, hdr, recs, mats, n_diag, tiles, V,
                            n_out, nbar, counters);
     return hipGetLastError();
 }

@@ -190,7 +190,55 @@ struct alignas(8) BatchHdr {
     int64_t P;        // pixels
     int64_t mat_off;  // offset of C_dd (n x n) then C_gd (n x g) in the matrix buffer
     int64_t tile0;    // first 64-pixel work item of the diagram
+    // swept diagrams (nx > 0): the voltages are formed from the sweep at
+    // grid_off in the matrix buffer: v0, e1, e2 (g each), then a0, da, a1,
+    // b0, db, b1 (see VGrid); P = nx * ny
+    int64_t grid_off;
+    int32_t nx, ny;
 };
+
+// An affine sweep of the gate voltages over a raster of nx x ny pixels,
+// pixel p = j nx + i:  V(i, j) = (v0 + a_i e1) + b_j e2 with a_i = i da + a0
+// (the last a_i is a1 itself) and b_j alike.  These are the values that
+// numpy's linspace and broadcast arithmetic give, rounded the same way (no
+// fused multiply-add), so a sweep and the explicit voltages it describes
+// give bitwise identical results.  on = 0: explicit voltages instead.
+struct VGrid {
+    double v0[kMaxGate], e1[kMaxGate], e2[kMaxGate];
+    double a0, da, a1, b0, db, b1;
+    int64_t nx, ny;
+    int32_t on, pad;
+};
+
+// point i of num equally spaced points from start to stop (step = (stop -
+// start) / (num - 1), 0 for one point), as numpy's linspace forms it
+// (contraction into fused multiply-adds is off in both: each product and
+// sum is rounded on its own)
+__device__ __forceinline__ double lin_point(int64_t i, int64_t num, double start, double step,
+                                            double stop)
+{
+#pragma clang fp contract(off)
+    const double t = (double)i * step;
+    return (num > 1 && i == num - 1) ? stop : t + start;
+}
+// v0_k + a e1_k + b e2_k, each operation rounded on its own
+__device__ __forceinline__ double sweep_volt(double v0, double e1, double e2, double a, double b)
+{
+#pragma clang fp contract(off)
+    const double s = v0 + a * e1;
+    return s + b * e2;
+}
+// the sweep coordinates (a, b) of pixel p
+__device__ __forceinline__ void grid_ab(const VGrid &G, int64_t p, double &a, double &b)
+{
+    a = lin_point(p % G.nx, G.nx, G.a0, G.da, G.a1);
+    b = lin_point(p / G.nx, G.ny, G.b0, G.db, G.b1);
+}
+// gate k's voltage at sweep coordinates (a, b)
+__device__ __forceinline__ double grid_v(const VGrid &G, int k, double a, double b)
+{
+    return sweep_volt(G.v0[k], G.e1[k], G.e2[k], a, b);
+}
 
 // The inputs of a DiagRec carried in a kernel's arguments (no host staging
 // buffer and no copy call): part 0 writes the header and C_dd, part 1 rows
@@ -230,11 +278,12 @@ hipError_t launch_prep(DiagRec *dr, int n_diag, int64_t *counters, hipStream_t s
 // clears the kCounterWords counters) and setup of every pixel; the per-block
 // counts {pixels, QP, doubled, QP failures} go to bstats[4 * block] for
 // setup_blocks(P, n_dot) blocks; x_out (P x N) / flags_out (P) are optional
-// copies of x*.  P >= 1.
+// copies of x*; grid, when given and on, replaces the voltages V.  P >= 1.
 int64_t setup_blocks(int64_t P, int n_dot);
 hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int64_t *counters,
                         int32_t *bstats, int n_dot, bool closed, hipStream_t s,
-                        double *x_out = nullptr, int32_t *flags_out = nullptr);
+                        double *x_out = nullptr, int32_t *flags_out = nullptr,
+                        const VGrid *grid = nullptr);
 // T = 0 argmin in FP64 over the candidate set of every pixel
 hipError_t launch_score_fp64(const DiagRec *dr, const PixRec *pr, int64_t P, int32_t *n_out,
                              int64_t *counters, int n_dot, hipStream_t s);
@@ -258,7 +307,7 @@ constexpr int kBwdReplicas = 8;
 constexpr int kBwdAccWords = kMaxDot * kMaxDot + kMaxDot * kMaxGate;
 hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P,
                            const double *gbar, const SavedRec *saved, double *acc,
-                           double *gradV, int n_dot, hipStream_t s);
+                           double *gradV, int n_dot, hipStream_t s, const VGrid *grid = nullptr);
 hipError_t launch_soft_bwd_final(const DiagRec *dr, double *acc, double *grad_cdd,
                                  double *grad_cgd, hipStream_t s);
 // charge-sensor response (qa_sensor.hip): the last n_sensor dots of dr are
@@ -274,8 +323,8 @@ hipError_t launch_sensor_jumps(int64_t P, int n_sensor, const double *u, double 
 // kernel over all 64-pixel work items
 hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *recs, int n_diag,
                              hipStream_t s);
-hipError_t launch_batch(const BatchHdr *hdr, const DiagRec *recs, int n_diag, int64_t tiles,
-                        const double *V, int32_t *n_out, double *nbar, int64_t *counters,
-                        int max_dot, int blocks, hipStream_t s);
+hipError_t launch_batch(const BatchHdr *hdr, const DiagRec *recs, const double *mats, int n_diag,
+                        int64_t tiles, const double *V, int32_t *n_out, double *nbar,
+                        int64_t *counters, int max_dot, int blocks, hipStream_t s);
 
 }  // namespace qa

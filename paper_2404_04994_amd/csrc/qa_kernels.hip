@@ -243,7 +243,8 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
                                                          int64_t *__restrict__ counters,
                                                          int32_t *__restrict__ bstats,
                                                          double *__restrict__ x_out,
-                                                         int32_t *__restrict__ flags_out)
+                                                         int32_t *__restrict__ flags_out,
+                                                         const VGrid vg)
 {
     __shared__ double sCdd[kMaxDot * kMaxDot];  // C_dd (input)
     __shared__ double sA[kMaxDot * kMaxDot];    // A (symmetric), from wave 0
@@ -304,8 +305,14 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             prep_tables_spread(dr, sA, sS, (int)blockIdx.x, (int)gridDim.x);
         }
     } else {
-        // x_u = C_gd V
-        for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * V[pc * g + j];
+        // x_u = C_gd V (V read, or formed from the sweep)
+        if (vg.on) {
+            double a, b;
+            grid_ab(vg, pc, a, b);
+            for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * grid_v(vg, j, a, b);
+        } else {
+            for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * V[pc * g + j];
+        }
         if (!is_dot) xu = 0.0;
         // analytic minimum: open x = x_u; closed adds (N_hat - 1^T x_u) C_dd 1 / (1^T C_dd 1)
         double x0 = xu;
@@ -511,15 +518,17 @@ int64_t setup_blocks(int64_t P, int n_dot)
 
 hipError_t launch_setup(DiagRec *dr, const double *V, int64_t P, PixRec *pr, int64_t *counters,
                         int32_t *bstats, int n_dot, bool closed, hipStream_t s, double *x_out,
-                        int32_t *flags_out)
+                        int32_t *flags_out, const VGrid *sweep)
 {
     const dim3 grid((unsigned)setup_blocks(P, n_dot)), block(kSetupThreads);
+    VGrid vg{};
+    if (sweep) vg = *sweep;
     if (closed)
         QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, true>), grid, block, 0, s, dr, V,
-                                                 P, pr, counters, bstats, x_out, flags_out));
+                                                 P, pr, counters, bstats, x_out, flags_out, vg));
     else
         QA_DISPATCH_NM(n_dot, hipLaunchKernelGGL((k_setup<NM_, false>), grid, block, 0, s, dr, V,
-                                                 P, pr, counters, bstats, x_out, flags_out));
+                                                 P, pr, counters, bstats, x_out, flags_out, vg));
     return hipGetLastError();
 }
 
@@ -992,7 +1001,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CPL > 0 ? 3
                                                   const double *__restrict__ gbar,
                                                   const SavedRec *__restrict__ saved,
                                                   double *__restrict__ acc,
-                                                  double *__restrict__ gradV)
+                                                  double *__restrict__ gradV,
+                                                  const VGrid vg)
 {
     constexpr int G = 1 << LG;
     constexpr int NU = 1 << (NM < kBwdMaxDot ? NM : kBwdMaxDot);
@@ -1026,10 +1036,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CPL > 0 ? 3
         // dot-wise quantities: lane d = lane mod NM computes dot d, then the
         // group gathers the vectors (G >= NM)
         const int d = lane & (NM - 1);
+        // the pixel's sweep coordinates (sweep input)
+        double va = 0.0, vb = 0.0;
+        if (vg.on) grid_ab(vg, p, va, vb);
+        auto volt = [&](int j) { return vg.on ? grid_v(vg, j, va, vb) : V[p * g + j]; };
         double zd = 0.0;
         if (d < n) {
             double s = 0.0;
-            for (int j = 0; j < g; ++j) s += sCgd[d * kMaxGate + j] * V[p * g + j];
+            for (int j = 0; j < g; ++j) s += sCgd[d * kMaxGate + j] * volt(j);
             zd = (double)sr->n0[d] - s;
         }
         double z[NM], g0[NM], gb[NM];
@@ -1144,7 +1158,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CPL > 0 ? 3
         }
         // gate column j: dL/dC_gd += dx V_j, dL/dV_j = sum_i C_gd,ij dx_i
         for (int j = lane; j < g; j += G) {
-            const double vj = V[p * g + j];
+            const double vj = volt(j);
             double gv = 0.0;
 #pragma unroll
             for (int i = 0; i < NM; ++i) {
@@ -1224,17 +1238,19 @@ __global__ __launch_bounds__(256) void k_soft_bwd_final(const DiagRec *__restric
 
 hipError_t launch_soft_bwd(const DiagRec *dr, const double *V, int64_t P, const double *gbar,
                            const SavedRec *saved, double *acc, double *gradV, int n_dot,
-                           hipStream_t s)
+                           hipStream_t s, const VGrid *sweep)
 {
+    VGrid vg{};
+    if (sweep) vg = *sweep;
     // acc: zeroed by the caller's prologue launch or left zero by the last
     // final kernel
     if (n_dot <= 8) {
         QA_DISPATCH_TAB(n_dot, hipLaunchKernelGGL((k_soft_bwd<LG_, NM_, CPL_>),
                                                   dim3(group_blocks(P, LG_, 2048)), dim3(256), 0,
-                                                  s, dr, V, P, gbar, saved, acc, gradV));
+                                                  s, dr, V, P, gbar, saved, acc, gradV, vg));
     } else {
         hipLaunchKernelGGL((k_soft_bwd<6, 16, 0>), dim3(group_blocks(P, 6, 2048)), dim3(256), 0,
-                           s, dr, V, P, gbar, saved, acc, gradV);
+                           s, dr, V, P, gbar, saved, acc, gradV, vg);
     }
     return hipGetLastError();
 }

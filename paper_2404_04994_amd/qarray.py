@@ -20,7 +20,9 @@ QA_OPEN, QA_CLOSED = 0, 1
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
 STATUS = {0: "QA_OK", 1: "QA_E_NULL", 2: "QA_E_SHAPE", 3: "QA_E_NOT_SYMMETRIC", 4: "QA_E_NOT_PD",
           5: "QA_E_RANGE", 6: "QA_E_UNSUPPORTED", 7: "QA_E_WORKSPACE", 8: "QA_E_DEVICE"}
-EXPORTS = ("qa_ground_state", "qa_ground_state_noalloc", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
+EXPORTS = ("qa_ground_state", "qa_ground_state_noalloc", "qa_ground_state_grid",
+           "qa_soft_charge_grid", "qa_soft_charge_backward_grid", "qa_ground_state_batched_grid",
+           "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward", "qa_saved_bytes",
            "qa_ground_state_batched", "qa_last_error", "qa_release", "qa_version",
            "qa_timing_enable", "qa_timing_reset", "qa_timing_sum", "qa_graphs_enable",
            "qa_time_kernels")
@@ -41,6 +43,26 @@ class Problem(C.Structure):
 
 
 FLAG_EXHAUSTIVE = 1
+
+
+class Grid(C.Structure):
+    """qa_grid: V(i, j) = (v0 + a_i e1) + b_j e2, a = linspace(a0, a1, nx),
+    b = linspace(b0, b1, ny), pixel p = j * nx + i."""
+    _fields_ = [("v0", C.POINTER(C.c_double)), ("e1", C.POINTER(C.c_double)),
+                ("e2", C.POINTER(C.c_double)), ("a0", C.c_double), ("a1", C.c_double),
+                ("b0", C.c_double), ("b1", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
+def make_grid(sweep):
+    """Grid struct from a sweep description (dict with v0, e1, e2, a0, a1, nx,
+    b0, b1, ny) plus the host arrays it points into (keep both alive)."""
+    arrs = tuple(np.ascontiguousarray(_host(sweep[k]), np.float64).ravel()
+                 for k in ("v0", "e1", "e2"))
+    dp = C.POINTER(C.c_double)
+    g = Grid(arrs[0].ctypes.data_as(dp), arrs[1].ctypes.data_as(dp), arrs[2].ctypes.data_as(dp),
+             float(sweep["a0"]), float(sweep["a1"]), float(sweep["b0"]), float(sweep["b1"]),
+             int(sweep["nx"]), int(sweep["ny"]))
+    return g, arrs
 
 
 class Stats(C.Structure):
@@ -66,6 +88,11 @@ def load():
         i64p = C.POINTER(C.c_int64)
         lib.qa_ground_state.argtypes = [pb, vp, C.c_int64, vp, st, vp]
         lib.qa_ground_state_noalloc.argtypes = [pb, vp, C.c_int64, vp, vp]
+        gp = C.POINTER(Grid)
+        lib.qa_ground_state_grid.argtypes = [pb, gp, vp, st, vp]
+        lib.qa_soft_charge_grid.argtypes = [pb, gp, vp, vp, st, vp]
+        lib.qa_soft_charge_backward_grid.argtypes = [pb, gp, vp, vp, vp, vp, vp, vp]
+        lib.qa_ground_state_batched_grid.argtypes = [pb, C.c_int32, gp, i64p, vp, vp, st, vp]
         lib.qa_soft_charge.argtypes = [pb, vp, C.c_int64, vp, vp, st, vp]
         lib.qa_continuous_min.argtypes = [pb, vp, C.c_int64, vp, vp, st, vp]
         lib.qa_soft_charge_backward.argtypes = [pb, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -90,6 +117,9 @@ def load():
         lib.qa_optimal_gate_voltages.restype = C.c_int
         lib.qa_virtual_gate_matrix.argtypes = [pb, vp]
         lib.qa_virtual_gate_matrix.restype = C.c_int
+        for f in ("qa_ground_state_grid", "qa_soft_charge_grid", "qa_soft_charge_backward_grid",
+                  "qa_ground_state_batched_grid"):
+            getattr(lib, f).restype = C.c_int
         for f in ("qa_ground_state", "qa_ground_state_noalloc", "qa_continuous_min", "qa_soft_charge", "qa_soft_charge_backward",
                   "qa_ground_state_batched"):
             getattr(lib, f).restype = C.c_int
@@ -154,6 +184,57 @@ def ground_state(cdd, cgd, V, closed=False, nhat=0, t=1.0, precision="fp64", str
                                _stream(stream)))
     del keep
     return (out, st.as_dict()) if stats else out
+
+
+def ground_state_grid(cdd, cgd, sweep, closed=False, nhat=0, t=1.0, precision="fp64",
+                      stream=None, stats=False, exhaustive=False, device="cuda"):
+    """qa_ground_state_grid: the ground state of every pixel of a sweep
+    (int32 (nx * ny, N) on the GPU; the voltages are formed in the kernel)."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, 0.0, t, precision,
+                            FLAG_EXHAUSTIVE if exhaustive else 0)
+    g, gkeep = make_grid(sweep)
+    out = torch.empty((g.nx * g.ny, pb.n_dot), dtype=torch.int32, device=device)
+    st = Stats() if stats else None
+    _check(lib.qa_ground_state_grid(C.byref(pb), C.byref(g), C.c_void_p(out.data_ptr()),
+                                    C.byref(st) if st else None, _stream(stream)))
+    del keep, gkeep
+    return (out, st.as_dict()) if stats else out
+
+
+def soft_charge_grid(cdd, cgd, sweep, kT, closed=False, nhat=0, t=1.0, stream=None,
+                     device="cuda"):
+    """qa_soft_charge_grid: (nbar float64 (P, N), saved buffer)."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, kT, t, "fp64")
+    g, gkeep = make_grid(sweep)
+    P = g.nx * g.ny
+    nbar = torch.empty((P, pb.n_dot), dtype=torch.float64, device=device)
+    saved = torch.empty(max(saved_bytes(P, pb.n_dot), 1), dtype=torch.uint8, device=device)
+    _check(lib.qa_soft_charge_grid(C.byref(pb), C.byref(g), C.c_void_p(nbar.data_ptr()),
+                                   C.c_void_p(saved.data_ptr()), None, _stream(stream)))
+    del keep, gkeep
+    return nbar, saved
+
+
+def soft_charge_backward_grid(cdd, cgd, sweep, kT, grad_nbar, saved, closed=False, nhat=0,
+                              t=1.0, want_V=True, stream=None):
+    """qa_soft_charge_backward_grid: (dL/dC_dd, dL/dC_gd, dL/dV or None)."""
+    lib = load()
+    pb, keep = make_problem(cdd, cgd, closed, nhat, kT, t, "fp64")
+    g, gkeep = make_grid(sweep)
+    P = g.nx * g.ny
+    gb = grad_nbar.to(torch.float64).contiguous()
+    dev = gb.device
+    dC = torch.empty((pb.n_dot, pb.n_dot), dtype=torch.float64, device=dev)
+    dG = torch.empty((pb.n_dot, pb.n_gate), dtype=torch.float64, device=dev)
+    dV = torch.empty((P, pb.n_gate), dtype=torch.float64, device=dev) if want_V else None
+    _check(lib.qa_soft_charge_backward_grid(
+        C.byref(pb), C.byref(g), C.c_void_p(gb.data_ptr()), C.c_void_p(saved.data_ptr()),
+        C.c_void_p(dC.data_ptr()), C.c_void_p(dG.data_ptr()),
+        C.c_void_p(dV.data_ptr()) if dV is not None else None, _stream(stream)))
+    del keep, gkeep
+    return dC, dG, dV
 
 
 NOALLOC_MAX_PIXELS = 65536
@@ -269,17 +350,23 @@ class Batch:
     Outputs: n (int32) and nbar (FP64) flat device tensors; rows of diagram d
     start at out_offsets[d] elements."""
 
-    def __init__(self, diagrams, device="cuda"):
+    def __init__(self, diagrams, device="cuda", sweeps=False):
+        """sweeps=True: every diagram is passed as its sweep description
+        (qa_ground_state_batched_grid; no voltages in device memory)."""
         self.diagrams = list(diagrams)
         nd = len(self.diagrams)
         self.problems = (Problem * nd)()
         self._keep = []
+        self.grids = (Grid * nd)() if sweeps else None
         v_off, p_cnt, o_off = [], [], []
         vo = oo = 0
         for i, d in enumerate(self.diagrams):
             pb, keep = make_problem(d.cdd, d.cgd, d.closed, d.nhat, d.kT, d.t, "fp64")
             self.problems[i] = pb
             self._keep.append(keep)
+            if sweeps:
+                self.grids[i], gkeep = make_grid(d.sweep)
+                self._keep.append(gkeep)
             v_off.append(vo)
             p_cnt.append(d.P)
             o_off.append(oo)
@@ -288,8 +375,9 @@ class Batch:
         self.v_offsets = np.array(v_off, np.int64)
         self.pix_counts = np.array(p_cnt, np.int64)
         self.out_offsets = np.array(o_off, np.int64)
-        self.V = torch.as_tensor(np.concatenate([np.ascontiguousarray(d.V, np.float64).ravel()
-                                                 for d in self.diagrams]), device=device)
+        self.V = None if sweeps else torch.as_tensor(
+            np.concatenate([np.ascontiguousarray(d.V, np.float64).ravel() for d in self.diagrams]),
+            device=device)
         self.n = torch.empty(max(oo, 1), dtype=torch.int32, device=device)
         self.nbar = torch.empty(max(oo, 1), dtype=torch.float64, device=device)
         self.pixels = int(self.pix_counts.sum())
@@ -298,11 +386,18 @@ class Batch:
         lib = load()
         i64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))
         st = Stats() if stats else None
-        _check(lib.qa_ground_state_batched(
-            self.problems, len(self.diagrams), C.c_void_p(self.V.data_ptr()), i64(self.v_offsets),
-            i64(self.pix_counts), i64(self.out_offsets), C.c_void_p(self.n.data_ptr()),
-            C.c_void_p(self.nbar.data_ptr()) if with_nbar else None,
-            C.byref(st) if st else None, _stream(stream)))
+        nbar = C.c_void_p(self.nbar.data_ptr()) if with_nbar else None
+        if self.grids is not None:
+            _check(lib.qa_ground_state_batched_grid(
+                self.problems, len(self.diagrams), self.grids, i64(self.out_offsets),
+                C.c_void_p(self.n.data_ptr()), nbar, C.byref(st) if st else None,
+                _stream(stream)))
+        else:
+            _check(lib.qa_ground_state_batched(
+                self.problems, len(self.diagrams), C.c_void_p(self.V.data_ptr()),
+                i64(self.v_offsets), i64(self.pix_counts), i64(self.out_offsets),
+                C.c_void_p(self.n.data_ptr()), nbar, C.byref(st) if st else None,
+                _stream(stream)))
         return st.as_dict() if stats else None
 
     def result(self, d):

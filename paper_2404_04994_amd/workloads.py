@@ -41,6 +41,9 @@ class Diagram:
     t: float = 1.0
     shape: tuple = ()
     meta: dict = field(default_factory=dict)
+    # the affine sweep that V rasters, when it is one: v0, e1, e2 (G each),
+    # a0, a1, nx, b0, b1, ny with V = sweep_voltages(sweep) (see there)
+    sweep: dict | None = None
 
     @property
     def n_dot(self) -> int:
@@ -74,6 +77,31 @@ def sweep2d(n_gate: int, gates, a, b, base=None) -> np.ndarray:
     V[:, gates[0]] = a[ii.ravel()]
     V[:, gates[1]] = b[jj.ravel()]
     return V
+
+
+def sweep_voltages(sw: dict) -> np.ndarray:
+    """The P x G voltages of an affine two-coordinate sweep: pixel
+    p = j * nx + i holds (v0 + a_i e1) + b_j e2 with a = linspace(a0, a1, nx)
+    and b = linspace(b0, b1, ny), in numpy's FP64 arithmetic (each operation
+    rounded on its own)."""
+    a = np.linspace(sw["a0"], sw["a1"], sw["nx"])
+    b = np.linspace(sw["b0"], sw["b1"], sw["ny"])
+    aa, bb = np.meshgrid(a, b)
+    v0, e1, e2 = (np.asarray(sw[k], np.float64) for k in ("v0", "e1", "e2"))
+    return v0[None, :] + aa.ravel()[:, None] * e1[None, :] + bb.ravel()[:, None] * e2[None, :]
+
+
+def gate_sweep(n_gate: int, gates, lo: float, hi: float, npix: int, base=None) -> dict:
+    """The sweep of gates (i0, i1) over linspace(lo, hi, npix) each, other
+    gates at ``base``: the same voltages as ``sweep2d`` (a swept gate's base
+    entry is replaced, so v0 is zero there)."""
+    v0 = np.zeros(n_gate) if base is None else np.array(base, np.float64)
+    v0[list(gates)] = 0.0
+    e1 = np.zeros(n_gate)
+    e2 = np.zeros(n_gate)
+    e1[gates[0]] = 1.0
+    e2[gates[1]] = 1.0
+    return dict(v0=v0, e1=e1, e2=e2, a0=lo, a1=hi, nx=npix, b0=lo, b1=hi, ny=npix)
 
 
 def _maxwell(diag, pairs, rng, lo_hi):
@@ -129,7 +157,8 @@ def double_dot(seed: int = 0, npix: int = 100, lo: float = -2.0, hi: float = 8.0
                     [rng.uniform(0.05, 0.15), rng.uniform(0.5, 1.0)]])
     ax = np.linspace(lo, hi, npix)
     return Diagram(cdd, cgd, sweep2d(2, (0, 1), ax, ax), shape=(npix, npix),
-                   meta=dict(workload="open double dot", seed=seed))
+                   meta=dict(workload="open double dot", seed=seed),
+                   sweep=gate_sweep(2, (0, 1), lo, hi, npix))
 
 
 def chain4(seed: int = 100, npix: int = 100, kT: float = 0.0) -> Diagram:
@@ -148,7 +177,8 @@ def chain4(seed: int = 100, npix: int = 100, kT: float = 0.0) -> Diagram:
     cgd[:, 4] = rng.uniform(0.0, 0.05, 4)
     ax = np.linspace(-2.0, 8.0, npix)
     return Diagram(cdd, cgd, sweep2d(5, (1, 2), ax, ax), kT=kT, shape=(npix, npix),
-                   meta=dict(workload="open 4-dot chain", seed=seed))
+                   meta=dict(workload="open 4-dot chain", seed=seed),
+                   sweep=gate_sweep(5, (1, 2), -2.0, 8.0, npix))
 
 
 def grid4x4(seed: int = 200, npix: int = 100, t: float = 1.0) -> Diagram:
@@ -175,7 +205,9 @@ def grid4x4(seed: int = 200, npix: int = 100, t: float = 1.0) -> Diagram:
     aa, bb = np.meshgrid(ax, ax)
     V = V0[None, :] + aa.ravel()[:, None] * d5[None, :] + bb.ravel()[:, None] * d6[None, :]
     return Diagram(cdd, cgd, V, t=t, shape=(npix, npix),
-                   meta=dict(workload="open 16-dot 4x4 array", seed=seed, rejected=rejected))
+                   meta=dict(workload="open 16-dot 4x4 array", seed=seed, rejected=rejected),
+                   sweep=dict(v0=V0, e1=d5, e2=d6, a0=-2.0, a1=8.0, nx=npix, b0=-2.0, b1=8.0,
+                              ny=npix))
 
 
 def ragged_diagram(d: int, npix: int = 64) -> Diagram:
@@ -201,7 +233,8 @@ def ragged_diagram(d: int, npix: int = 64) -> Diagram:
     kT = float(rng.uniform(0.0, 0.02))
     ax = np.linspace(-2.0, 8.0, npix)
     return Diagram(cdd, cgd, sweep2d(n, (0, 1), ax, ax), closed=closed, nhat=nhat, kT=kT,
-                   shape=(npix, npix), meta=dict(workload="ragged batch item", d=d, layout=layout))
+                   shape=(npix, npix), meta=dict(workload="ragged batch item", d=d, layout=layout),
+                   sweep=gate_sweep(n, (0, 1), -2.0, 8.0, npix))
 
 
 def ragged_batch(n_diag: int = 4096, npix: int = 64, start: int = 0):
@@ -219,6 +252,7 @@ class AdjointCase:
     cdd_target: np.ndarray
     cgd_target: np.ndarray
     shape: tuple
+    sweep: dict | None = None
 
 
 def adjoint_case(seed: int = 400, npix: int = 100, kT: float = 0.02) -> AdjointCase:
@@ -253,7 +287,8 @@ def adjoint_case(seed: int = 400, npix: int = 100, kT: float = 0.02) -> AdjointC
     eps = np.triu(eps) + np.triu(eps, 1).T
     cdd_t = cdd * (1.0 + 0.05 * eps)
     cgd_t = cgd * (1.0 + 0.05 * rng.standard_normal((9, 9)))
-    return AdjointCase(cdd, cgd, V, kT, cdd_t, cgd_t, (npix, npix))
+    return AdjointCase(cdd, cgd, V, kT, cdd_t, cgd_t, (npix, npix),
+                       gate_sweep(9, (0, 1), -2.0, 8.0, npix, base=base))
 
 
 def paper_example():

@@ -145,3 +145,40 @@ def test_noalloc_validation(qa):
     bad, kb = qa.make_problem(np.array([[1.0, -2.0], [-2.0, 1.0]]), GOOD_CGD)
     assert f(C.byref(bad), C.c_void_p(16), 4, C.c_void_p(16), None) == 4
     assert b"positive definite" in lib.qa_last_error()
+
+
+def test_grid_validation(qa):
+    """The sweep entry points validate the descriptor (NULLs, sizes, finite
+    values) before any device work."""
+    lib = qa.load()
+    pb, keep = qa.make_problem(GOOD_CDD, GOOD_CGD)
+    sw = dict(v0=[0.0, 0.1], e1=[1.0, 0.0], e2=[0.0, 1.0], a0=-1.0, a1=1.0, nx=4, b0=0.0, b1=2.0,
+              ny=3)
+    assert lib.qa_ground_state_grid(C.byref(pb), None, C.c_void_p(16), None, None) == 1
+    g, gk = qa.make_grid(dict(sw, nx=0))
+    assert lib.qa_ground_state_grid(C.byref(pb), C.byref(g), C.c_void_p(16), None, None) == 2
+    g, gk = qa.make_grid(dict(sw, ny=1 << 20, nx=1 << 12))
+    assert lib.qa_ground_state_grid(C.byref(pb), C.byref(g), C.c_void_p(16), None, None) == 2
+    g, gk = qa.make_grid(dict(sw, a1=float("inf")))
+    assert lib.qa_ground_state_grid(C.byref(pb), C.byref(g), C.c_void_p(16), None, None) == 5
+    g, gk = qa.make_grid(dict(sw, e2=[0.0, float("nan")]))
+    assert lib.qa_ground_state_grid(C.byref(pb), C.byref(g), C.c_void_p(16), None, None) == 5
+    g, gk = qa.make_grid(sw)
+    assert lib.qa_ground_state_grid(C.byref(pb), C.byref(g), None, None, None) == 1
+    g.e1 = None
+    assert lib.qa_ground_state_grid(C.byref(pb), C.byref(g), C.c_void_p(16), None, None) == 1
+    soft, sk = qa.make_problem(GOOD_CDD, GOOD_CGD, kT=0.0)
+    g, gk = qa.make_grid(sw)
+    assert lib.qa_soft_charge_grid(C.byref(soft), C.byref(g), C.c_void_p(16), None, None,
+                                   None) == 5
+    grids = (qa.Grid * 2)()
+    grids[0], gk0 = qa.make_grid(sw)
+    grids[1], gk1 = qa.make_grid(dict(sw, ny=0))
+    probs = (qa.Problem * 2)()
+    probs[0] = probs[1] = pb
+    off = np.zeros(2, np.int64)
+    st = lib.qa_ground_state_batched_grid(probs, 2, grids, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          C.c_void_p(16), None, None, None)
+    assert st == 2 and b"diagram 1" in lib.qa_last_error()
+    assert lib.qa_ground_state_batched_grid(probs, 2, None, off.ctypes.data_as(
+        C.POINTER(C.c_int64)), C.c_void_p(16), None, None, None) == 1
