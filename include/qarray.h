@@ -308,12 +308,13 @@ qa_status qa_timing_sum(void *hip_stream, double *ms_out, int64_t *calls_out);
 /* Kernel timing (diagnostics).  Runs qa_ground_state's device work once
  * (n_out_dev receives the ground state), then on hip_stream: an event,
  * `reps` back-to-back launches of the setup kernel (prologue, continuous
- * minimum, candidate setup), an event, `reps` back-to-back launches of the
- * T = 0 scorer the problem selects, an event.  Waits, and writes the mean
- * milliseconds per launch: ms_out[0] the setup kernel, ms_out[1] the scorer.
- * No events separate launches of one kernel, so the mean is the kernel's
- * duration plus the dispatch gap between back-to-back launches.
- * reps in [1, 100000]; P >= 1. */
+ * minimum, candidate setup), an event, `reps` (setup, scorer) pairs, an
+ * event.  Waits, and writes the mean milliseconds per launch: ms_out[0] the
+ * setup kernel (first interval / reps), ms_out[1] the T = 0 scorer the
+ * problem selects (second interval less the first, / reps), i.e. the
+ * scorer as it runs in a call, right after the setup that wrote its inputs.
+ * No events separate the launches, so each mean includes the dispatch gap
+ * between back-to-back launches.  reps in [1, 100000]; P >= 1. */
 qa_status qa_time_kernels(const qa_problem *prob, const double *V_dev, int64_t P,
                           int32_t *n_out_dev, int32_t reps, double *ms_out, void *hip_stream);
 

@@ -121,6 +121,9 @@ constexpr int kPrecFP32 = 1, kPrecX3 = 2, kPrecX2 = 3;
 #ifndef QA_BOUND_B_LDS
 #define QA_BOUND_B_LDS 1
 #endif
+#ifndef QA_BOUND_B_REGS
+#define QA_BOUND_B_REGS 0
+#endif
 
 // MODE kDense: the floor/ceil box.  kPruned: the thresholded candidate set
 // (Sec. 3.2.2), n0 + b with b a subset of the pixel's free dots.  kClosed:
@@ -723,7 +726,14 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
     __syncthreads();
     auto bop_lds = [&](int ct) -> uint4 { return sB[ct][lane]; };
 #if QA_BOUND_B_LDS
-    auto bop = bop_lds;
+    // the first QA_BOUND_B_REGS column tiles' operands also in registers
+    // (less LDS traffic per product), the others read from LDS
+    // (split-BF16 forms only: the FP32 form's registers are taken)
+    constexpr int kBRegs = PREC == kPrecFP32 ? 0 : QA_BOUND_B_REGS;
+    uint4 bw[kBRegs > 0 ? kBRegs : 1];
+#pragma unroll
+    for (int ct = 0; ct < kBRegs; ++ct) bw[ct] = col_operand(ct);
+    auto bop = [&](int ct) -> uint4 { return ct < kBRegs ? bw[ct] : bop_lds(ct); };
 #else
     // in registers for the whole kernel
     uint4 bw[16];

@@ -322,20 +322,34 @@ class SoftCharge(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, cdd, cgd, V, kT, closed=False, nhat=0, t=1.0):
-        nbar, saved = soft_charge(cdd, cgd, V, kT, closed, nhat, t)
-        ctx.save_for_backward(cdd, cgd, V)
+        # the library reads the matrices on the host: one copy of both (a
+        # single device-to-host transfer when they live on the GPU), kept for
+        # the backward
+        n, g = cdd.shape[0], cgd.shape[1]
+        if cdd.is_cuda or cgd.is_cuda:
+            both = torch.cat([cdd.detach().reshape(-1), cgd.detach().reshape(-1).to(cdd.device)])
+            both = both.to(torch.float64).cpu().numpy()
+            cdd_h, cgd_h = both[:n * n].reshape(n, n), both[n * n:].reshape(n, g)
+        else:
+            cdd_h, cgd_h = _host(cdd), _host(cgd)
+        nbar, saved = soft_charge(cdd_h, cgd_h, V, kT, closed, nhat, t)
+        ctx.save_for_backward(V)
+        ctx.host = (cdd_h, cgd_h)
+        ctx.devs = (cdd.device, cdd.dtype, cgd.device, cgd.dtype)
         ctx.saved_buf = saved
         ctx.args = (float(kT), bool(closed), int(nhat), float(t))
         return nbar
 
     @staticmethod
     def backward(ctx, grad_nbar):
-        cdd, cgd, V = ctx.saved_tensors
+        (V,) = ctx.saved_tensors
+        cdd_h, cgd_h = ctx.host
+        cdev, cdt, gdev, gdt = ctx.devs
         kT, closed, nhat, t = ctx.args
-        dC, dG, dV = soft_charge_backward(cdd, cgd, V, kT, grad_nbar, ctx.saved_buf, closed, nhat,
-                                          t, want_V=ctx.needs_input_grad[2])
-        dC = dC.to(cdd.device, cdd.dtype) if ctx.needs_input_grad[0] else None
-        dG = dG.to(cgd.device, cgd.dtype) if ctx.needs_input_grad[1] else None
+        dC, dG, dV = soft_charge_backward(cdd_h, cgd_h, V, kT, grad_nbar, ctx.saved_buf, closed,
+                                          nhat, t, want_V=ctx.needs_input_grad[2])
+        dC = dC.to(cdev, cdt) if ctx.needs_input_grad[0] else None
+        dG = dG.to(gdev, gdt) if ctx.needs_input_grad[1] else None
         dV = dV.to(V.device, V.dtype).view_as(V) if ctx.needs_input_grad[2] else None
         return dC, dG, dV, None, None, None, None
 
