@@ -312,38 +312,61 @@ __global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
     // The work queue is sharded over the kCounterSlots counter lines: slot s
     // hands out items s, s + kCounterSlots, ... (each shard keeps the plan's
     // largest-first order).  A block drains its home slot, then takes what
-    // is left in the others; a plain read skips shards already exhausted, so
-    // no single address sees every block's atomics.
+    // is left in the others, moving on once its count on a shard runs past
+    // the end, so no single address sees every block's atomics.
     const int home = blockIdx.x & (kCounterSlots - 1);
     int shard = 0;
-    for (;;) {
-        if (lane == 0) {
-            int64_t it = tiles;
-            for (; shard < kCounterSlots; ++shard) {
-                const int sl = (home + shard) & (kCounterSlots - 1);
-                int64_t *cur = &counters[sl * C_NUM + C_WORK];
-                if ((int64_t)sl + kCounterSlots * *(volatile int64_t *)cur >= tiles) continue;
-                it = (int64_t)sl + kCounterSlots * (int64_t)atomicAdd((unsigned long long *)cur, 1ull);
-                if (it < tiles) break;
-            }
-            sitem = it;
+    // lane 0: an atomic on the current shard (its raw count; -1 once every
+    // shard is exhausted), and the work item such a count stands for (the
+    // next shards are tried when it is past the end)
+    auto issue = [&]() -> int64_t {
+        if (shard >= kCounterSlots) return -1;
+        const int sl = (home + shard) & (kCounterSlots - 1);
+        return (int64_t)atomicAdd((unsigned long long *)&counters[sl * C_NUM + C_WORK], 1ull);
+    };
+    auto take = [&](int64_t raw) -> int64_t {
+        while (raw >= 0) {
+            const int64_t it = (int64_t)((home + shard) & (kCounterSlots - 1)) + kCounterSlots * raw;
+            if (it < tiles) return it;
+            ++shard;
+            raw = issue();
         }
+        return tiles;
+    };
+    // The next item's atomic is issued when an item starts and read when it
+    // ends, so its latency hides behind the item's work.  The diagram's A
+    // and table stay in LDS while the items come from the same diagram (its
+    // items are consecutive in a shard), and the search over the headers
+    // runs only when an item leaves the current diagram.
+    if (lane == 0) sitem = take(issue());
+    int d = -1;
+    int64_t d_lo = 0, d_hi = 0;  // items [d_lo, d_hi) belong to diagram d
+    BatchHdr h{};
+    for (;;) {
         __syncthreads();
         const int64_t item = sitem;
         if (item >= tiles) break;
-        // the diagram of this work item: last d with tile0 <= item
-        int lo = 0, hi = n_diag - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (hdr[mid].tile0 <= item) lo = mid;
-            else hi = mid - 1;
+        int64_t raw = -1;
+        if (lane == 0) raw = issue();
+        if (item < d_lo || item >= d_hi) {
+            // the diagram of this work item: last d with tile0 <= item
+            int lo = 0, hi = n_diag - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (hdr[mid].tile0 <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            d = lo;
+            h = hdr[d];
+            d_lo = h.tile0;
+            d_hi = d + 1 < n_diag ? hdr[d + 1].tile0 : tiles;
+            const DiagRec *dn = recs + d;
+            for (int e = lane; e < kMaxDot * kMaxDot; e += 64) sA[e] = dn->A[e];
+            if (NM <= 8)
+                for (int e = lane; e < 256; e += 64) sh[e] = dn->hs[e];
+            __syncthreads();
         }
-        const BatchHdr h = hdr[lo];
-        const DiagRec *dr = recs + lo;
-        for (int e = lane; e < kMaxDot * kMaxDot; e += 64) sA[e] = dr->A[e];
-        if (NM <= 8)
-            for (int e = lane; e < 256; e += 64) sh[e] = dr->hs[e];
-        __syncthreads();
+        const DiagRec *dr = recs + d;
         const int64_t p = (item - h.tile0) * 64 + lane;
         if (p < h.P) {
             int qp = 0, fail = 0, dbl = 0, gap = 0;
@@ -369,7 +392,8 @@ __global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
             ndbl += dbl;
             ngap += gap;
         }
-        __syncthreads();  // sA and sitem are rewritten by the next item
+        __syncthreads();  // sA and sitem are rewritten for the next item
+        if (lane == 0) sitem = take(raw);
     }
     // wave totals -> counters
     npix = (int64_t)group_sum<6>((double)npix);

@@ -98,9 +98,23 @@ __device__ __forceinline__ double base_state(const double *__restrict__ A, int n
     return 0.5 * u0;
 }
 
+// 1/sqrt(a) for the Cholesky pivots: the hardware estimate refined by two
+// Newton steps r <- r (3/2 - a r^2 / 2) (each squares the relative error),
+// within an ulp for the positive normal pivots of a definite system.
+__device__ __forceinline__ double rsqrt_nr(double a)
+{
+    double r = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    r = r * fma(-h * r, r, 1.5);
+    return r * fma(-h * r, r, 1.5);
+}
+
 // Cholesky solve of an SPD system held as a packed lower triangle, M fixed.
+// The factor's diagonal is kept as its reciprocal, so the factorisation and
+// both substitutions multiply where they would divide (no square root, no
+// division).  On return a holds L below the diagonal and 1 / L_jj on it.
 template <int M>
-__host__ __device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2], double (&b)[M])
+__device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2], double (&b)[M])
 {
 #define LIDX(i, j) ((i) * ((i) + 1) / 2 + (j))
 #pragma unroll
@@ -108,9 +122,8 @@ __host__ __device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2]
         double d = a[LIDX(j, j)];
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= a[LIDX(j, k)] * a[LIDX(j, k)];
-        d = sqrt(d);
-        a[LIDX(j, j)] = d;
-        const double inv = 1.0 / d;
+        const double inv = rsqrt_nr(d);
+        a[LIDX(j, j)] = inv;
 #pragma unroll
         for (int i = j + 1; i < M; ++i) {
             double s = a[LIDX(i, j)];
@@ -124,14 +137,14 @@ __host__ __device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2]
         double s = b[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= a[LIDX(i, k)] * b[k];
-        b[i] = s / a[LIDX(i, i)];
+        b[i] = s * a[LIDX(i, i)];
     }
 #pragma unroll
     for (int i = M - 1; i >= 0; --i) {
         double s = b[i];
 #pragma unroll
         for (int k = i + 1; k < M; ++k) s -= a[LIDX(k, i)] * b[k];
-        b[i] = s / a[LIDX(i, i)];
+        b[i] = s * a[LIDX(i, i)];
     }
 #undef LIDX
 }
@@ -148,7 +161,7 @@ __host__ __device__ __forceinline__ void chol_solve(double (&a)[M * (M + 1) / 2]
 // grows (Chandrasekaran's method), at most N rounds.  Returns false when the
 // iteration did not settle (x is then the last iterate, clipped at 0).
 template <int NM, bool CLOSED>
-__host__ __device__ bool qp_solve(const DiagRec *__restrict__ dr, const double (&xu)[NM], double (&x)[NM])
+__device__ bool qp_solve(const DiagRec *__restrict__ dr, const double (&xu)[NM], double (&x)[NM])
 {
     constexpr int M = NM + (CLOSED ? 1 : 0);
     const int n = dr->n;
@@ -364,7 +377,7 @@ __device__ __forceinline__ void prep_inverse(const double *sCdd, int n, double *
                 double mk[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) mk[q] = __shfl(m[q], (k << 2) | (tid & 3));
-                const double r = 1.0 / piv;
+                const double r = recip_nr(piv);
                 const double mr = -mik * r;  // the new column k
                 // branch-free selects (the four cases of the pivot map)
 #pragma unroll
@@ -447,21 +460,17 @@ __device__ __forceinline__ double row_bcast_block(double x)
 // complement C_LL - C_LH C_HH^{-1} C_HL = (A_LL)^{-1} in its low block and
 // C_HH^{-1} C_HL in its high-low block; the whole 16 x 16 matrix is copied to
 // S when S is given (identity rows and columns past n).
-__device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, double *M,
+__device__ __forceinline__ void prep_inverse_wave(const double (&m0)[4], int n, double *M,
                                                   double *red, double *S = nullptr)
 {
     // lane = 16 b + j: column j of rows 4 b .. 4 b + 3 (a DPP row of the
     // wave holds four matrix rows), so the pivot column of a lane's rows is a
     // broadcast within its DPP row and the pivot row a broadcast of one DPP
-    // row to the others (the gfx950 row swaps); no LDS round trip per pivot
+    // row to the others (the gfx950 row swaps); no LDS round trip per pivot.
+    // m0: the caller's C_dd in that layout, identity rows and columns past n.
     const int tid = threadIdx.x;
     const int j = tid & 15, b = tid >> 4;
-    double m[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = 4 * b + q;
-        m[q] = (i < n && j < n) ? sCdd[i * kMaxDot + j] : (i == j ? 1.0 : 0.0);
-    }
+    double m[4] = {m0[0], m0[1], m0[2], m0[3]};
     static_for_dev<0, kMaxDot>([&](auto kc) {
         constexpr int kk = decltype(kc)::value;
         constexpr int k = (kk + 8) & (kMaxDot - 1);
@@ -471,16 +480,20 @@ __device__ __forceinline__ void prep_inverse_wave(const double *sCdd, int n, dou
         }
         if (k < n) {
             // M[k][j] (pivot row) and M[4 b + q][k] (pivot column)
+            // the pivot M[k][k] straight from its lane (16 (k / 4) + k,
+            // element k % 4), so its reciprocal starts while the pivot row
+            // is still being broadcast
+            const uint64_t pu = (uint64_t)__double_as_longlong(m[k & 3]);
+            constexpr int lk = 16 * (k >> 2) + k;
+            const double piv = __longlong_as_double(
+                (long long)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pu, lk) |
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(pu >> 32), lk)
+                             << 32)));
+            const double r = recip_nr(piv);
             const double rowk = row_bcast_block<(k >> 2)>(m[k & 3]);
             double mik[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) mik[q] = dppd<kDppRowBcast0 + k>(m[q]);
-            const uint64_t pu = (uint64_t)__double_as_longlong(rowk);
-            const double piv = __longlong_as_double(
-                (long long)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pu, k) |
-                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(pu >> 32), k)
-                             << 32)));
-            const double r = 1.0 / piv;
             const double t1 = rowk * r;
             // branch-free selects (the four cases of the pivot map)
 #pragma unroll
@@ -538,9 +551,9 @@ __device__ __forceinline__ void prep_store_core(DiagRec *dr, const double *M, co
 // global wave index and the number of waves of the grid).
 __device__ __forceinline__ void prep_tables_spread(DiagRec *dr, const double *M,
                                                    const double *S = nullptr, int first = -1,
-                                                   int stride = 0)
+                                                   int stride = 0, int n_dots = -1)
 {
-    const int n = dr->n;
+    const int n = n_dots >= 0 ? n_dots : dr->n;
     const int lane = threadIdx.x & (kWave - 1);
     const int gw = first >= 0 ? first : blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     const int nw = first >= 0 ? stride : gridDim.x * (blockDim.x / kWave);

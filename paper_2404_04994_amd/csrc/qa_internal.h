@@ -74,6 +74,19 @@ __device__ __forceinline__ double dppd(double x)
                        ((uint64_t)dpp32<CTRL>((uint32_t)(u >> 32)) << 32);
     return __longlong_as_double((long long)r);
 }
+// 1/a for the pivots of the eliminations: the hardware estimate refined by
+// two Newton steps r <- r + r (1 - a r) (each squares the relative error),
+// within an ulp of the rounded quotient for the normal, finite pivots of a
+// positive definite elimination; five dependent operations instead of the
+// ten of the correctly rounded division.
+__device__ __forceinline__ double recip_nr(double a)
+{
+    double r = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-a, r, 1.0);
+    return fma(r, e, r);
+}
 constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
 // lane i of every 16-lane row to the whole row
 constexpr int kDppRowBcast0 = 0x150;

@@ -189,7 +189,7 @@ __device__ __forceinline__ void gj_pivot(double (&r)[NM], double &v, int k, int 
 #pragma unroll
     for (int q = 0; q < NM; ++q) pr[q] = __shfl(r[q], src, kWave);
     const double pv = __shfl(v, src, kWave);
-    const double rp = 1.0 / piv;
+    const double rp = recip_nr(piv);
     if (dot == k) {
 #pragma unroll
         for (int q = 0; q < NM; ++q) r[q] = pr[q] * rp;
@@ -214,7 +214,7 @@ __device__ __forceinline__ void gj_pivot_row(double (&r)[NM], double &v, int dot
 #pragma unroll
     for (int q = 0; q < NM; ++q) pr[q] = dppd<kDppRowBcast0 + K>(r[q]);
     const double pv = dppd<kDppRowBcast0 + K>(v);
-    const double rp = 1.0 / piv;
+    const double rp = recip_nr(piv);
     if (dot == K) {
 #pragma unroll
         for (int q = 0; q < NM; ++q) r[q] = pr[q] * rp;
@@ -253,40 +253,68 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     __shared__ double sS[kMaxDot * kMaxDot];    // the elimination after the high pivots, from wave 0
     __shared__ double sG[kMaxGate * NM];        // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
-    // the inputs into LDS in one pass; meanwhile 16 lanes of wave 0 form
-    // C_dd 1 and 1^T C_dd 1 from the record
-    const int n = dr->n, g = dr->g;
-    for (int e = threadIdx.x; e < kMaxDot * kMaxDot; e += blockDim.x) sCdd[e] = dr->Cdd[e];
-    for (int e = threadIdx.x; e < kMaxGate * NM; e += blockDim.x) {
-        const int j = e / NM, i = e % NM;
-        sG[e] = dr->Cgd[i * kMaxGate + j];
-    }
-    if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
-    if (threadIdx.x < kMaxDot) {
-        // the row's loads all issued before the first add
-        const int r = threadIdx.x;
-        double row[kMaxDot];
+    // Staging in one round trip: every load below is issued before any of
+    // them is used.  C_gd (transposed) by all threads, C_dd by waves 1..4,
+    // wave 0 its four C_dd rows per lane for the inverse (lane 16 b + j:
+    // column j of rows 4 b .. 4 b + 3) and lanes 0..15 of wave 0 one row
+    // each for C_dd 1; the pixel waves of 16-dot groups also fetch their
+    // voltages (lane j: V_j and V_16+j).
+    const int tid = threadIdx.x;
+    const int n = dr->n, g = dr->g, nhat = dr->nhat;
+    const double t_in = dr->t;
+    const bool pixel_wave = tid >= kWave;
+    const int tp = tid - kWave;  // thread index among the pixel waves
+    const int dot = tp & (NM - 1);
+    const int base = (tid & (kWave - 1)) & ~(NM - 1);
+    // wave w of block b takes group-set w * gridDim.x + b: the groups of one
+    // wave are adjacent pixels (similar active sets, so the union of their QP
+    // pivots stays small) while the waves of one block come from across the
+    // sweep, so the QP-heavy regions are shared out among the blocks
+    const int64_t p = ((int64_t)(tp / kWave) * gridDim.x + blockIdx.x) * (kWave / NM) +
+                      (tp & (kWave - 1)) / NM;
+    const int64_t pc = p < P ? p : P - 1;  // groups past the end repeat the last pixel
+    const bool is_dot = dot < n;
+    const double gv = (tid < kMaxGate * NM) ? dr->Cgd[(tid % NM) * kMaxGate + tid / NM] : 0.0;
+    const int ce = tid - kWave;
+    const double cv = (ce >= 0 && ce < kMaxDot * kMaxDot) ? dr->Cdd[ce] : 0.0;
+    double m4[4], row[kMaxDot];
+    if (!pixel_wave) {
+        const int j = tid & 15, b = tid >> 4;
 #pragma unroll
-        for (int q = 0; q < kMaxDot; ++q) row[q] = (r < n && q < n) ? dr->Cdd[r * kMaxDot + q] : 0.0;
+        for (int q = 0; q < 4; ++q) m4[q] = dr->Cdd[(4 * b + q) * kMaxDot + j];
+        const int r = tid & 15;
+#pragma unroll
+        for (int q = 0; q < kMaxDot; ++q) row[q] = dr->Cdd[r * kMaxDot + q];
+    }
+    double v0 = 0.0, v1 = 0.0;
+    if (NM == 16 && pixel_wave && !vg.on) {
+        if (dot < g) v0 = V[pc * g + dot];
+        if (16 + dot < g) v1 = V[pc * g + 16 + dot];
+    }
+    if (tid < kMaxGate * NM) sG[tid] = gv;
+    if (ce >= 0 && ce < kMaxDot * kMaxDot) sCdd[ce] = cv;
+    if (tid < 4) cnt[tid] = 0;
+    if (!pixel_wave) {
+        const int j = tid & 15, b = tid >> 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 4 * b + q;
+            m4[q] = (i < n && j < n) ? m4[q] : (i == j ? 1.0 : 0.0);
+        }
+        // C_dd 1 and 1^T C_dd 1 (lanes 0..15, row r = lane)
+        const int r = tid & 15;
         double c = 0.0;
 #pragma unroll
-        for (int q = 0; q < kMaxDot; ++q) c += row[q];
-        sc[r] = c;
+        for (int q = 0; q < kMaxDot; ++q) c += (r < n && q < n) ? row[q] : 0.0;
         double oc = c;
 #pragma unroll
         for (int off = 8; off >= 1; off >>= 1) oc += __shfl_xor(oc, off, 16);
-        if (r == 0) red[4] = oc;
+        if (tid < kMaxDot) sc[r] = c;
+        if (tid == 0) red[4] = oc;
     }
     __syncthreads();
     const double one_c = red[4];
 
-    const bool pixel_wave = threadIdx.x >= kWave;
-    const int tp = threadIdx.x - kWave;  // thread index among the pixel waves
-    const int dot = tp & (NM - 1);
-    const int base = (threadIdx.x & (kWave - 1)) & ~(NM - 1);
-    const int64_t p = (int64_t)blockIdx.x * (kSetupPixThreads / NM) + tp / NM;
-    const int64_t pc = p < P ? p : P - 1;  // groups past the end repeat the last pixel
-    const bool is_dot = dot < n;
     double xu = 0.0, x = 0.0;
     int n0 = 0, k = -1, flags = 0, cflags = 0;
     uint32_t fm = 0;
@@ -294,22 +322,28 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     if (!pixel_wave) {
         // the inverse is the block's critical path: its wave issues first
         __builtin_amdgcn_s_setprio(3);
-        prep_inverse_wave(sCdd, n, sA, red, sS);
-        __builtin_amdgcn_s_setprio(0);
+        prep_inverse_wave(m4, n, sA, red, sS);
         // a grid of at least 256 blocks: wave 0 of block b fills energy-table
         // entry b while the pixel waves finish (off the kernel's tail)
         if (gridDim.x >= 256) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            prep_tables_spread(dr, sA, sS, (int)blockIdx.x, (int)gridDim.x);
+            prep_tables_spread(dr, sA, sS, (int)blockIdx.x, (int)gridDim.x, n);
         }
+        __builtin_amdgcn_s_setprio(0);
     } else {
         // x_u = C_gd V (V read, or formed from the sweep)
         if (vg.on) {
             double a, b;
             grid_ab(vg, pc, a, b);
             for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * grid_v(vg, j, a, b);
+        } else if constexpr (NM == 16) {
+            // V_j from lane j of the group (prefetched before the barrier)
+            static_for_dev<0, kMaxGate>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if (j < g) xu += sG[j * NM + dot] * dppd<kDppRowBcast0 + (j & 15)>(j < 16 ? v0 : v1);
+            });
         } else {
             for (int j = 0; j < g; ++j) xu += sG[j * NM + dot] * V[pc * g + j];
         }
@@ -317,12 +351,12 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         // analytic minimum: open x = x_u; closed adds (N_hat - 1^T x_u) C_dd 1 / (1^T C_dd 1)
         double x0 = xu;
         if (CLOSED) {
-            const double lam = ((double)dr->nhat - group_dsum<NM>(xu)) / one_c;
+            const double lam = ((double)nhat - group_dsum<NM>(xu)) / one_c;
             x0 = is_dot ? xu + lam * sc[dot] : 0.0;
         }
         x = x0;
         uint32_t W = group_ballot<NM>(is_dot && x0 < 0.0);
-        if (CLOSED && dr->nhat == 0) {
+        if (CLOSED && nhat == 0) {
             // x = 0 is the only admissible point of a closed empty array
             flags = W ? 1 : 0;
             x = 0.0;
@@ -378,7 +412,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         }
 
         // candidate set (Sec. 3.2): base n0, free dots, closed: k raised free dots
-        double t = dr->t;
+        double t = t_in;
         bool freed = false;
         for (int iter = 0; iter < 80; ++iter) {
             // the box starts at floor(x* + 1e-9): a continuous minimum on an
@@ -390,7 +424,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             if (!CLOSED) break;
             const int sum0 = group_isum<NM>(n0);
             const int nfree = __popc(group_ballot<NM>(freed));
-            const int need = dr->nhat - sum0;
+            const int need = nhat - sum0;
             if (need >= 0 && need <= nfree) { k = need; break; }
             if (t >= 1.0) {  // |sum x* - N_hat| < 1 makes this unreachable
                 k = need < 0 ? 0 : nfree;
@@ -421,10 +455,17 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     if (pixel_wave) {
         // g0 = A (n0 - x_u) and U(n0) = 1/2 (n0 - x_u)^T g0 (Eq. free_energy)
         const double z = is_dot ? (double)n0 - xu : 0.0;
+        // column `dot` of A, all of it read before the first use (the loads
+        // overlap instead of each waiting in turn)
+        double acol[NM];
+        static_for_dev<0, NM>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            acol[q] = sA[q * kMaxDot + dot];
+        });
         double g0 = 0.0;
         static_for_dev<0, NM>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
-            g0 += sA[q * kMaxDot + dot] * group_bcast<NM, q>(z, base);
+            g0 += acol[q] * group_bcast<NM, q>(z, base);
         });
         const double u0 = 0.5 * group_dsum<NM>(z * g0);
         // energy of the guess state n0 + b (b = the bits gm) relative to
@@ -435,7 +476,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             double ab = 0.0;
             static_for_dev<0, NM>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                ab += (gm >> q & 1u) ? sA[q * kMaxDot + dot] : 0.0;
+                ab += (gm >> q & 1u) ? acol[q] : 0.0;
             });
             eg = group_dsum<NM>((gm >> dot & 1u) ? g0 + 0.5 * ab : 0.0);
         }
@@ -445,9 +486,14 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         double sv = 0.0, Kb = 0.0, mu = 0.0;
         if (NM == 16 && n >= 13) {
             const int hd = dot >= 8 ? dot : 8;
+            double srow[8];
             static_for_dev<0, 8>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
-                sv += sS[hd * kMaxDot + 8 + q] * group_bcast<NM, (8 + q) & (NM - 1)>(z, base);
+                srow[q] = sS[hd * kMaxDot + 8 + q];
+            });
+            static_for_dev<0, 8>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                sv += srow[q] * group_bcast<NM, (8 + q) & (NM - 1)>(z, base);
             });
             sv = dot >= 8 ? sv : 0.0;
             Kb = 0.5 * group_dsum<NM>(z * sv) - u0;
