@@ -209,7 +209,23 @@ __device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
     }
     if (!feasible) {
         qp = 1;
-        const bool ok = closed ? qp_solve<NM, true>(dr, xu, x) : qp_solve<NM, false>(dr, xu, x);
+        bool ok = false;
+        if constexpr (NM <= 8) {
+            // the QP at the diagram's own size (its factorisation is cubic in
+            // the order; dots n.. of x are zero already).  The rest of the
+            // path stays at NM: one copy of it per dot count made the kernel
+            // too large for the instruction cache.
+            static_for_dev<1, NM + 1>([&](auto kc) {
+                constexpr int K = decltype(kc)::value;
+                if (n == K) {
+                    const double(&xk)[K] = *reinterpret_cast<const double(*)[K]>(&xu[0]);
+                    double(&yk)[K] = *reinterpret_cast<double(*)[K]>(&x[0]);
+                    ok = closed ? qp_solve<K, true>(dr, xk, yk) : qp_solve<K, false>(dr, xk, yk);
+                }
+            });
+        } else {
+            ok = closed ? qp_solve<NM, true>(dr, xu, x) : qp_solve<NM, false>(dr, xu, x);
+        }
         fail = ok ? 0 : 1;
     }
     int n0[NM];
