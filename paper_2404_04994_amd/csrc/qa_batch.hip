@@ -311,8 +311,10 @@ __device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
     return scored;
 }
 
+// Up to 8 dots: three waves per SIMD (168 registers, a few spilled) hide
+// more of each lane's FP64 chains than two at full register use.
 template <int NM>
-__global__ __launch_bounds__(64) void k_batch(const BatchHdr *__restrict__ hdr,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NM <= 8 ? 3 : 1))) void k_batch(const BatchHdr *__restrict__ hdr,
                                               const DiagRec *__restrict__ recs,
                                               const double *__restrict__ mats, int n_diag,
                                               int64_t tiles, const double *__restrict__ V,
