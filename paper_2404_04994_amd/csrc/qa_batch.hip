@@ -179,13 +179,16 @@ __device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
                                                int &dbl, int &gap)
 {
     const int n = dr->n, g = dr->g;
+    // x_u = C_gd V, gate by gate: each voltage is read (or formed) once,
+    // and every x_u,i still sums over j in increasing order
     double xu[NM], x[NM];
 #pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        double s = 0.0;
-        if (i < n)
-            for (int j = 0; j < g; ++j) s += dr->Cgd[i * kMaxGate + j] * volt(j);
-        xu[i] = s;
+    for (int i = 0; i < NM; ++i) xu[i] = 0.0;
+    for (int j = 0; j < g; ++j) {
+        const double vj = volt(j);
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+            if (i < n) xu[i] += dr->Cgd[i * kMaxGate + j] * vj;
     }
     // analytic minimum first (Sec. 3.1.1), the QP only when it is negative
     double lam = 0.0;
@@ -234,7 +237,22 @@ __device__ __forceinline__ int64_t batch_pixel(const DiagRec *__restrict__ dr,
     const int flags = candidate_set<NM>(dr, closed, x, n0, fm, k);
     dbl = (flags & 4) ? 1 : 0;
     double g0[NM];
-    const double u0 = base_state<NM>(A, n, n0, xu, g0);
+    double u0 = 0.0;
+    if constexpr (NM <= 8) {
+        // at the diagram's own size too (quadratic in it; the padding of A
+        // adds zeros only)
+#pragma unroll
+        for (int i = 0; i < NM; ++i) g0[i] = 0.0;
+        static_for_dev<1, NM + 1>([&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            if (n == K)
+                u0 = base_state<K>(A, n, *reinterpret_cast<const int(*)[K]>(&n0[0]),
+                                   *reinterpret_cast<const double(*)[K]>(&xu[0]),
+                                   *reinterpret_cast<double(*)[K]>(&g0[0]));
+        });
+    } else {
+        u0 = base_state<NM>(A, n, n0, xu, g0);
+    }
     if (NM <= 8 && fm == (1u << n) - 1u) {
         // dense box: table-driven walk
         const bool soft = nbout != nullptr && dr->kT > 0.0;
