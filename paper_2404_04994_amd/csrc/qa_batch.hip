@@ -67,8 +67,9 @@ hipError_t launch_prep_batch(const BatchHdr *hdr, const double *mats, DiagRec *r
 // are compile-time constants, and gray(16 o + k) = gray(16 o) ^ gray(k).
 // Pass 1 finds the smallest energy; pass 2 finds the lexicographically
 // smallest state at that energy (the rank brev(s)), the runner-up energy and,
-// for kT > 0, the Boltzmann sums (weights exp2 in FP32 of an FP64 argument,
-// relative error below 3e-6 for every weight above e^-60; sums in FP64).
+// for kT > 0, the Boltzmann sums (weights by the hardware exp2 in FP32 of
+// an FP64 argument, relative error below 3e-6 for every weight above e^-60;
+// sums in FP64).
 template <int NM>
 __device__ __forceinline__ int64_t dense_small(const double *__restrict__ sh,
                                                const double (&g0)[NM], int n, int k, double kT,
@@ -140,7 +141,7 @@ __device__ __forceinline__ int64_t dense_small(const double *__restrict__ sh,
                         e2 = fmin(e2, e);
                     }
                     if (soft) {
-                        const float w = exp2f((float)((e1 - e) * c));
+                        const float w = __builtin_amdgcn_exp2f((float)((e1 - e) * c));
                         sblk += w;
                         if (gk & 1u) t0 += w;
                         if (gk & 2u) t1 += w;
