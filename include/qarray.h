@@ -85,9 +85,10 @@ typedef enum { QA_OPEN = 0, QA_CLOSED = 1 } qa_mode;
  * The integer result is the same for all four: the near-tie re-score
  * replaces the approximate argmin by the FP64 one whenever the approximate
  * runner-up lies within the certified error band.  The matrix-core forms are
- * used for open arrays at T = 0 with n_dot >= 9, over the dense box (t = 1)
- * or the thresholded sub-box of each pixel (t < 1, Sec. 3.2.2); elsewhere
- * the FP64 form runs regardless of the request. */
+ * used at T = 0 with n_dot >= 9: for open arrays over the dense box (t = 1)
+ * or the thresholded sub-box of each pixel (t < 1, Sec. 3.2.2), for closed
+ * arrays over the subsets of the free dots that raise the charge to N_hat
+ * (Sec. 3.2); elsewhere the FP64 form runs regardless of the request. */
 typedef enum {
     QA_PREC_FP64 = 0,
     QA_PREC_FP32 = 1,

@@ -1,6 +1,7 @@
-// qa_mfma.hip -- matrix-core scorer for the floor/ceil box (Sec. 3.2.1) and
-// its thresholded sub-boxes (Sec. 3.2.2) at T = 0 (Eq. argmin), 9 <= N <= 16
-// dots, open arrays.
+// qa_mfma.hip -- matrix-core scorer for the floor/ceil box (Sec. 3.2.1), its
+// thresholded sub-boxes (Sec. 3.2.2) and, for closed arrays, the subsets of
+// the free dots with the required number raised, at T = 0 (Eq. argmin),
+// 9 <= N <= 16 dots.
 //
 // Every candidate of pixel p is n0 + b, b in {0,1}^N, and (Eq. free_energy)
 //     U(n0 + b) - U(n0) = b^T g + 1/2 b^T A b,       g = A (n0 - x_u).
