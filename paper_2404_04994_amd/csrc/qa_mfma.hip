@@ -647,38 +647,10 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
     const int li = lane & 15;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    // the first pixel's record, requested before the tables are staged:
-    // lane i < 16 holds g0_i and n0_i, lanes 8..15 also s_{i-8}, lane 0 K,
-    // lane 1 mu (vector loads, one pixel ahead from here on)
-    double gnext = 0.0;
-    int nnext = 0, knext = 0;
-    uint32_t fnext = 0;
-    float snext = 0.0f, egnext = 0.0f;
-    if (wave < P) {
-        gnext = pr[wave].g0[li];
-        nnext = pr[wave].n0[li];
-        snext = (li >= 8) ? pr[wave].s[li - 8] : (li == 1 ? pr[wave].mu : pr[wave].K);
-        if (PRUNED) fnext = pr[wave].free;
-        if (CLOSED) knext = pr[wave].k;
-        egnext = pr[wave].eg;
-    }
+    // the diagram's scalars first (their loads lead the staging)
     const int n = dr->n;
     const int nh = n - 8;
     const int nrt = 1 << (nh - 4);
-    for (int e = threadIdx.x; e < 128; e += blockDim.x) {
-        sT1[e / 8][e % 8] = dr->T1[e / 8][e % 8];
-        sT2[e / 8][e % 8] = dr->T2[e / 8][e % 8];
-        sT1d[e / 8][e % 8] = dr->T1d[e / 8][e % 8];
-        sT2d[e / 8][e % 8] = dr->T2d[e / 8][e % 8];
-    }
-    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
-        sH[e] = dr->Hhi[e];
-        sHd[e] = dr->Hhid[e];
-        sLd[e] = dr->hlod[e];
-        sHs[e] = dr->Hs[e];
-        sHlo[e] = dr->hlo[e];
-    }
-    if (threadIdx.x == 0) { sflag = 0; sgap = 0; srows = 0; scand = 0; }
     const float sumabs = dr->sumabs;
     const float hsabs = dr->sabsS;
     // closed arrays: w and 1 / (2 gamma) of the low-sum term of the bound
@@ -690,6 +662,41 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
         wabs += fabsf(wb[j]);
     }
     const float inv2g = CLOSED ? dr->inv2g : 0.0f;
+    // the first pixel's record, requested before the tables are staged:
+    // lane i < 16 holds g0_i and n0_i, lanes 8..15 also s_{i-8}, lane 0 K,
+    // lane 1 mu (vector loads, one pixel ahead from here on)
+    // (read unconditionally, from the last pixel for waves past the end:
+    // P >= 1, and no branch holds the staging below behind these loads)
+    const int64_t w0 = wave < P ? wave : P - 1;
+    double gnext = pr[w0].g0[li];
+    int nnext = pr[w0].n0[li];
+    float snext = (li >= 8) ? pr[w0].s[li - 8] : (li == 1 ? pr[w0].mu : pr[w0].K);
+    uint32_t fnext = PRUNED ? pr[w0].free : 0u;
+    int knext = CLOSED ? pr[w0].k : 0;
+    float egnext = pr[w0].eg;
+    {
+        // the diagram's tables, one entry per thread (the blocks are 256
+        // threads): every read issued before the first LDS write, so the
+        // staging is one round trip
+        const int e = threadIdx.x;
+        const int r8 = (e & 127) >> 3, c8 = e & 7;
+        const float t1 = dr->T1[r8][c8], t2 = dr->T2[r8][c8];
+        const double t1d = dr->T1d[r8][c8], t2d = dr->T2d[r8][c8];
+        const float hh = dr->Hhi[e], hs = dr->Hs[e], hl = dr->hlo[e];
+        const double hhd = dr->Hhid[e], hld = dr->hlod[e];
+        if (e < 128) {
+            sT1[r8][c8] = t1;
+            sT2[r8][c8] = t2;
+            sT1d[r8][c8] = t1d;
+            sT2d[r8][c8] = t2d;
+        }
+        sH[e] = hh;
+        sHd[e] = hhd;
+        sLd[e] = hld;
+        sHs[e] = hs;
+        sHlo[e] = hl;
+    }
+    if (threadIdx.x == 0) { sflag = 0; sgap = 0; srows = 0; scand = 0; }
     __syncthreads();
 
     // pixel-independent column operands (as in the dense scorer), from the
