@@ -858,10 +858,14 @@ __global__ __launch_bounds__(256) void k_soft_fwd_tab(const DiagRec *__restrict_
 {
     constexpr int G = 1 << LG;
     __shared__ double sH[256];
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) sH[i] = dr->hs[i];
-    __syncthreads();
+    // the scalars and the table entry of this thread (blocks of 256) read
+    // together, one round trip before the pixel loop
     const int n = dr->n;
-    const double ikT = 1.0 / dr->kT;
+    const double kT = dr->kT;
+    const double hs = dr->hs[threadIdx.x];
+    sH[threadIdx.x] = hs;
+    __syncthreads();
+    const double ikT = 1.0 / kT;
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
@@ -1058,19 +1062,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CPL > 0 ? 3
     __shared__ double sdA[kMaxDot * kMaxDot];
     __shared__ double sdG[kMaxDot * kMaxGate];
     __shared__ double sH[CPL > 0 ? 256 : 1];  // whole-box table h(s) (table form)
-    for (int i = threadIdx.x; i < kMaxDot * kMaxDot; i += blockDim.x) {
-        sA[i] = dr->A[i];
-        sdA[i] = 0.0;
-        if (CPL > 0) sH[i] = dr->hs[i];
-    }
-    for (int i = threadIdx.x; i < kMaxDot * kMaxGate; i += blockDim.x) {
-        sCgd[i] = dr->Cgd[i];
-        sdG[i] = 0.0;
+    static_assert(kMaxDot * kMaxDot == 256 && kMaxDot * kMaxGate == 512, "staging layout");
+    // every staging read issued before the first LDS write (blocks of 256
+    // threads: one A / table entry and two C_gd entries each), with the
+    // scalars, so the staging is one round trip
+    const int n = dr->n, g = dr->g;
+    const double kT = dr->kT;
+    {
+        const int t = threadIdx.x;
+        const double a = dr->A[t];
+        const double h = CPL > 0 ? dr->hs[t] : 0.0;
+        const double c0 = dr->Cgd[t], c1 = dr->Cgd[t + 256];
+        sA[t] = a;
+        sdA[t] = 0.0;
+        if (CPL > 0) sH[t] = h;
+        sCgd[t] = c0;
+        sCgd[t + 256] = c1;
+        sdG[t] = 0.0;
+        sdG[t + 256] = 0.0;
     }
     for (int i = threadIdx.x; i < NU; i += blockDim.x) sU[i] = 0.0;
     __syncthreads();
-    const int n = dr->n, g = dr->g;
-    const double ikT = 1.0 / dr->kT;
+    const double ikT = 1.0 / kT;
     const int lane = threadIdx.x & (G - 1);
     const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LG;
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
