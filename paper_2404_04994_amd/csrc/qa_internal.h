@@ -56,10 +56,14 @@ __device__ __forceinline__ void block_add_counter(int64_t *counters, int which, 
 // (exchange with lane ^ 1, lane ^ 2, then the mirror images within 8 and 16
 // lanes, each an involution, so after four steps every lane of a row holds
 // the row's result), then the row swaps of gfx950 for 16 and 32 lanes.
+// Every pattern used here (quad permutations, row mirrors, row broadcasts) has
+// a valid source lane for every lane, so the move needs no "old" value: the
+// plain DPP move, not the update form, whose old operand costs a v_mov per
+// use.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp32(uint32_t x)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ float dppf(float x)
