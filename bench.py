@@ -44,8 +44,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sha(path):
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+def sha(*paths):
+    h = hashlib.sha256()
+    for path in paths:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def scorer_sources():
+    """The sources the scorer kernel is compiled from (its file and the
+    header of device helpers it includes)."""
+    csrc = os.path.join(ROOT, "paper_2404_04994_amd", "csrc")
+    return [os.path.join(csrc, "qa_mfma.hip"), os.path.join(csrc, "qa_internal.h")]
 
 
 def timed_calls(fn, steps, warmup, torch):
@@ -235,8 +245,8 @@ def counters_entry(args):
     if not os.path.exists(COUNTERS_FILE):
         return None
     tr = json.load(open(COUNTERS_FILE))
-    src = os.path.join(ROOT, "paper_2404_04994_amd", "csrc", "qa_mfma.hip")
-    if tr.get("source_sha") != sha(src) or tr.get("precision") != args.precision or args.exhaustive:
+    if (tr.get("source_sha") != sha(*scorer_sources()) or tr.get("precision") != args.precision
+            or args.exhaustive):
         return None
     return tr
 
