@@ -1092,10 +1092,14 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
                     m = __builtin_fminf(m, __builtin_fminf(d[2], d[3]));
                 }
                 const int code = 4 * t + cg;
+                // the group codes by bitwise selects (the compiler turns
+                // nested conditional moves into branches here)
+                const int lt1 = -(int)(m < b1), lt2 = -(int)(m < b2);
+                const int n2 = a2 ^ ((code ^ a2) & lt2);
                 b3 = __builtin_amdgcn_fmed3f(b2, b3, m);
-                a2 = (m < b1) ? a1 : ((m < b2) ? code : a2);
+                a2 = n2 ^ ((a1 ^ n2) & lt1);
                 b2 = __builtin_amdgcn_fmed3f(b1, b2, m);
-                a1 = (m < b1) ? code : a1;
+                a1 = a1 ^ ((code ^ a1) & lt1);
                 b1 = __builtin_fminf(b1, m);
                 // one group's products in flight at a time (their results
                 // are 16 registers)
