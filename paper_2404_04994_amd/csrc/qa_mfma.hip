@@ -668,9 +668,16 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
     // (read unconditionally, from the last pixel for waves past the end:
     // P >= 1, and no branch holds the staging below behind these loads)
     const int64_t w0 = wave < P ? wave : P - 1;
+    // byte offset of the lane's float in the record (s_{li-8}, mu or K),
+    // fixed per lane, so the per-pixel read is one load without branches
+    const int soff = li >= 8 ? (int)offsetof(PixRec, s) + 4 * (li - 8)
+                             : (li == 1 ? (int)offsetof(PixRec, mu) : (int)offsetof(PixRec, K));
+    auto rec_f = [&](int64_t i) -> float {
+        return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(pr + i) + soff);
+    };
     double gnext = pr[w0].g0[li];
     int nnext = pr[w0].n0[li];
-    float snext = (li >= 8) ? pr[w0].s[li - 8] : (li == 1 ? pr[w0].mu : pr[w0].K);
+    float snext = rec_f(w0);
     uint32_t fnext = PRUNED ? pr[w0].free : 0u;
     int knext = CLOSED ? pr[w0].k : 0;
     float egnext = pr[w0].eg;
@@ -776,8 +783,7 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
         if (p + nwaves < P) {
             gnext = pr[p + nwaves].g0[li];
             nnext = pr[p + nwaves].n0[li];
-            snext = (li >= 8) ? pr[p + nwaves].s[li - 8]
-                              : (li == 1 ? pr[p + nwaves].mu : pr[p + nwaves].K);
+            snext = rec_f(p + nwaves);
             if (PRUNED) fnext = pr[p + nwaves].free;
             if (CLOSED) knext = pr[p + nwaves].k;
             egnext = pr[p + nwaves].eg;
