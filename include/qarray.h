@@ -223,7 +223,9 @@ qa_status qa_soft_charge(const qa_problem *prob, const double *V_dev, int64_t P,
  * The candidate set is piecewise constant in the inputs, so only the
  * energies carry gradient; they are recomputed, not read back.  This is not
  * in the paper (which notes that the discrete model defeats autograd,
- * Sec. 6); it differentiates the softargmin exactly.  n_dot <= 12. */
+ * Sec. 6); it differentiates the softargmin exactly.  n_dot <= 12 (each
+ * block keeps one FP64 sum per candidate state, 2^N of them, in its local
+ * memory); larger problems return QA_E_UNSUPPORTED. */
 qa_status qa_soft_charge_backward(const qa_problem *prob, const double *V_dev, int64_t P,
                                   const double *grad_nbar_dev, const void *saved_dev,
                                   double *grad_cdd_dev, double *grad_cgd_dev,
