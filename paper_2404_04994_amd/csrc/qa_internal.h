@@ -179,7 +179,8 @@ struct alignas(8) PixRec {
     uint32_t free;        // dots that take both roundings
     int32_t k;            // closed: number of raised free dots; -1 open
     int32_t flags;        // bit0 QP path, bit1 QP failure, bit2 threshold doubled
-    uint32_t guess;       // a state of the candidate set: the free dots whose x* rounds up
+    uint32_t guess;       // a state of the candidate set: the free dots whose x* rounds up,
+                          // then the best single flip of a free dot if it lowers the energy
                           // (closed: the k free dots with the largest fractional parts)
     // lower bound of the states of a high part b_hi (N >= 13, open):
     // K + b_hi^T s + 1/2 b_hi^T S b_hi, s = S (n0 - x_u)_hi

@@ -462,6 +462,7 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
             constexpr int q = decltype(qc)::value;
             acol[q] = sA[q * kMaxDot + dot];
         });
+        const double aii = sA[dot * kMaxDot + dot];
         double g0 = 0.0;
         static_for_dev<0, NM>([&](auto qc) {
             constexpr int q = decltype(qc)::value;
@@ -479,6 +480,23 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
                 ab += (gm >> q & 1u) ? acol[q] : 0.0;
             });
             eg = group_dsum<NM>((gm >> dot & 1u) ? g0 + 0.5 * ab : 0.0);
+            if (!CLOSED) {
+                // Open arrays: the rounding of x* takes the best single flip
+                // of a free dot when it lowers the energy (flipping dot i of b
+                // changes it by (1 - 2 b_i) (g0 + A b)_i + A_ii / 2).  The
+                // guess stays a state of the candidate set; its lower energy
+                // leaves fewer high parts for the scorer (on random sweeps
+                // one flip reaches nearly all that a full descent does).
+                const double gd = g0 + ab;
+                const double de =
+                    (fm >> dot & 1u) ? ((gm >> dot & 1u) ? -gd : gd) + 0.5 * aii : INFINITY;
+                const double dmin = group_min<4>(de);
+                const uint32_t at = group_ballot<NM>(de == dmin);
+                if (dmin < 0.0 && at) {
+                    gm ^= 1u << (__ffs(at) - 1);  // the lowest dot of the best flip
+                    eg += dmin;
+                }
+            }
         }
         // terms of the lower bound of the bound-ordered scorer (N >= 13):
         // s = S z_hi and K = 1/2 z_hi^T s - U(n0) with S = (C_dd,HH)^{-1};

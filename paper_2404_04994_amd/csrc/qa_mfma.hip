@@ -880,8 +880,9 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
                 if (li >> j & 1) v += (lane < 16) ? g[8 + j] : g[12 + j];
             ptab[lane] = v;
         }
-        // The rows to score.  The setup's guess (the rounding of x*; closed:
-        // the k free dots with the largest fractional parts) is a state of
+        // The rows to score.  The setup's guess (the rounding of x* and its
+        // best single flip when that lowers the energy; closed: the k free
+        // dots with the largest fractional parts) is a state of
         // the candidate set; its energy E_g (FP64 in the setup, rounded to
         // FP32) bounds the approximate best from above (by E_g + 1.1 delta),
         // so a high part whose bound exceeds E_g + margin + delta holds

@@ -218,7 +218,9 @@ def test_bound_order_equals_exhaustive(qa, prec):
     assert diff == 0
     assert sb["candidates"] == se["candidates"] == d.P << 16
     assert se["scored"] == se["candidates"]
-    assert 16 * 256 * d.P <= sb["scored"] < sb["candidates"] // 2
+    # every pixel scores at least the row (256 states) that holds its argmin;
+    # the bound order leaves most of the box unscored
+    assert 256 * d.P <= sb["scored"] < sb["candidates"] // 8
 
 
 @pytest.mark.parametrize("n_dot,seed", [(13, 601), (14, 602), (15, 603), (16, 604)])
