@@ -917,8 +917,10 @@ qa_status batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
     BatchPlan plan;
     auto it = g_tune.find(sig);
     if (it == g_tune.end() && g_autotune) {
-        // time every candidate launch shape once on this very batch (each run
-        // writes the same outputs) and keep the fastest
+        // time every candidate launch shape on this very batch (each run
+        // writes the same outputs; the better of two runs, so that a cold
+        // first launch or a stray slow one does not decide) and keep the
+        // fastest
         int dev = 0, cus = 256;
         QA_HIP(hipGetDevice(&dev));
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -934,15 +936,17 @@ qa_status batched(const qa_problem *probs, int32_t n_diag, const double *V_dev,
             if ((st = upload_plan(w, plan, n_diag))) return st;
             for (int mult : {2, 4, 8, 16}) {
                 const int blocks = cus * mult;
-                QA_HIP(hipEventRecord(e0, w->stream));
-                if ((st = enqueue_batch(w, w->stream, n_diag, plan, V_dev, n_out_dev, nbar_out_dev,
-                                        blocks)))
-                    return st;
-                QA_HIP(hipEventRecord(e1, w->stream));
-                QA_HIP(hipEventSynchronize(e1));
-                float ms = 0.0f;
-                QA_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) { best_ms = ms; best = BatchTune{blocks, by_size != 0}; }
+                for (int rep = 0; rep < 2; ++rep) {
+                    QA_HIP(hipEventRecord(e0, w->stream));
+                    if ((st = enqueue_batch(w, w->stream, n_diag, plan, V_dev, n_out_dev,
+                                            nbar_out_dev, blocks)))
+                        return st;
+                    QA_HIP(hipEventRecord(e1, w->stream));
+                    QA_HIP(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    QA_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) { best_ms = ms; best = BatchTune{blocks, by_size != 0}; }
+                }
             }
         }
         (void)hipEventDestroy(e0);
