@@ -98,3 +98,28 @@ def test_bound_is_exact_for_a_real_low_part():
     blo = -np.linalg.solve(A[L, L], gp)
     b = np.concatenate([blo, bhi])
     assert abs((b @ g + 0.5 * b @ A @ b) - (K + bhi @ s + 0.5 * bhi @ S @ bhi)) < 1e-12
+
+
+@pytest.mark.parametrize("n,seed", [(13, 21), (16, 22)])
+def test_single_flip_delta(n, seed):
+    """The setup's guess takes its best single flip: flipping dot i of b
+    changes E(b) = b^T g + 1/2 b^T A b by (1 - 2 b_i) (g + A b)_i + A_ii / 2
+    (checked against the energies directly, for random states)."""
+    rng = np.random.default_rng(seed)
+    cdd, cgd = W.random_maxwell(n, seed)
+    A = np.linalg.inv(cdd)
+    x_u = cgd @ rng.uniform(-1, 3, cgd.shape[1])
+    y = np.floor(x_u) - x_u
+    g = A @ y
+
+    def E(b):
+        return b @ g + 0.5 * b @ A @ b
+
+    for _ in range(20):
+        b = rng.integers(0, 2, n).astype(float)
+        gd = g + A @ b
+        for i in range(n):
+            f = b.copy()
+            f[i] = 1.0 - f[i]
+            de = (1.0 - 2.0 * b[i]) * gd[i] + 0.5 * A[i, i]
+            assert abs((E(f) - E(b)) - de) <= 1e-12 * (1.0 + abs(E(b)))
