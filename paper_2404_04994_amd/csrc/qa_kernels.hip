@@ -232,9 +232,10 @@ __device__ __forceinline__ void gj_pivot_row(double (&r)[NM], double &v, int dot
 // take 7 * 64 / NM pixels through x_u, the QP and the candidate set, which
 // need C_dd but not its inverse; a barrier then hands A to the pixel waves
 // for the base-state gradient.  (Eight waves: two blocks fill a CU at four
-// waves per SIMD; five-wave blocks left a fifth of the grid waiting for a
-// second round.)
+// waves per SIMD; four-wave blocks measured the same, five-wave blocks left
+// a fifth of the grid waiting for a second round.)
 constexpr int kSetupThreads = kWave + kSetupPixThreads;
+static_assert(kSetupThreads >= kMaxDot * kMaxDot, "C_dd staging: one entry per thread");
 
 template <int NM, bool CLOSED>
 __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec *__restrict__ dr,
@@ -254,11 +255,12 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     __shared__ double sG[kMaxGate * NM];        // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
     // Staging in one round trip: every load below is issued before any of
-    // them is used.  C_gd (transposed) by all threads, C_dd by waves 1..4,
-    // wave 0 its four C_dd rows per lane for the inverse (lane 16 b + j:
-    // column j of rows 4 b .. 4 b + 3) and lanes 0..15 of wave 0 one row
-    // each for C_dd 1; the pixel waves of 16-dot groups also fetch their
-    // voltages (lane j: V_j and V_16+j).
+    // them is used.  C_gd (transposed, only the gates the diagram has) and
+    // C_dd by the first threads, wave 0 also
+    // its four C_dd rows per lane for the inverse (lane 16 b + j: column j of
+    // rows 4 b .. 4 b + 3) and lanes 0..15 of wave 0 one row each for
+    // C_dd 1; the pixel waves of 16-dot groups also fetch their voltages
+    // (lane j: V_j and V_16+j).
     const int tid = threadIdx.x;
     const int n = dr->n, g = dr->g, nhat = dr->nhat;
     const double t_in = dr->t;
@@ -274,9 +276,15 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
                       (tp & (kWave - 1)) / NM;
     const int64_t pc = p < P ? p : P - 1;  // groups past the end repeat the last pixel
     const bool is_dot = dot < n;
-    const double gv = (tid < kMaxGate * NM) ? dr->Cgd[(tid % NM) * kMaxGate + tid / NM] : 0.0;
-    const int ce = tid - kWave;
-    const double cv = (ce >= 0 && ce < kMaxDot * kMaxDot) ? dr->Cdd[ce] : 0.0;
+    // (C_gd transposed: entry e = j NM + i, the gates j < g only)
+    constexpr int kGv = (kMaxGate * NM + kSetupThreads - 1) / kSetupThreads;
+    double gv[kGv];
+#pragma unroll
+    for (int r = 0; r < kGv; ++r) {
+        const int e = tid + r * kSetupThreads;
+        gv[r] = (e < g * NM) ? dr->Cgd[(e % NM) * kMaxGate + e / NM] : 0.0;
+    }
+    const double cv = (tid < kMaxDot * kMaxDot) ? dr->Cdd[tid] : 0.0;
     double m4[4], row[kMaxDot];
     if (!pixel_wave) {
         const int j = tid & 15, b = tid >> 4;
@@ -291,8 +299,12 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         if (dot < g) v0 = V[pc * g + dot];
         if (16 + dot < g) v1 = V[pc * g + 16 + dot];
     }
-    if (tid < kMaxGate * NM) sG[tid] = gv;
-    if (ce >= 0 && ce < kMaxDot * kMaxDot) sCdd[ce] = cv;
+#pragma unroll
+    for (int r = 0; r < kGv; ++r) {
+        const int e = tid + r * kSetupThreads;
+        if (e < g * NM) sG[e] = gv[r];
+    }
+    if (tid < kMaxDot * kMaxDot) sCdd[tid] = cv;
     if (tid < 4) cnt[tid] = 0;
     if (!pixel_wave) {
         const int j = tid & 15, b = tid >> 4;

@@ -305,6 +305,18 @@ def test_max_gates_and_dots(qa, oracle):
     V12 = rng.uniform(-1, 3, (300, n))
     check_gs(qa, oracle, c12, g12, V12, closed=True, nhat=9)
     check_gs(qa, oracle, c12, g12, V12, closed=True, nhat=9, t=0.5)
+    # 13 dots and 32 gates: the setup stages C_gd over more entries than the
+    # block has threads
+    n = 13
+    c13 = np.diag(rng.uniform(1.0, 1.4, n))
+    for i in range(n - 1):
+        c13[i, i + 1] = c13[i + 1, i] = -rng.uniform(0.1, 0.3)
+    g13 = rng.uniform(0.0, 0.1, (n, 32))
+    g13[np.arange(n), np.arange(n)] += rng.uniform(0.5, 1.0, n)
+    V13 = rng.uniform(-1, 4, (300, 32))
+    check_gs(qa, oracle, c13, g13, V13)
+    check_gs(qa, oracle, c13, g13, V13, precision="bf16x3")
+    check_gs(qa, oracle, c13, g13, V13, closed=True, nhat=10)
 
 
 def test_empty_input(qa):
