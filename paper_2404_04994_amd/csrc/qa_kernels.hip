@@ -255,12 +255,11 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
     __shared__ double sG[kMaxGate * NM];        // C_gd transposed: sG[j * NM + i]
     __shared__ int cnt[4];
     // Staging in one round trip: every load below is issued before any of
-    // them is used.  C_gd (transposed, only the gates the diagram has) and
-    // C_dd by the first threads, wave 0 also
-    // its four C_dd rows per lane for the inverse (lane 16 b + j: column j of
-    // rows 4 b .. 4 b + 3) and lanes 0..15 of wave 0 one row each for
-    // C_dd 1; the pixel waves of 16-dot groups also fetch their voltages
-    // (lane j: V_j and V_16+j).
+    // them is used.  C_gd (transposed, only the gates the diagram has) by
+    // the first threads, C_dd by wave 0 (four entries per lane, the layout of
+    // the inverse: lane 16 b + j holds column j of rows 4 b .. 4 b + 3); the
+    // pixel waves of 16-dot groups also fetch their voltages (lane j: V_j
+    // and V_16+j).
     const int tid = threadIdx.x;
     const int n = dr->n, g = dr->g, nhat = dr->nhat;
     const double t_in = dr->t;
@@ -284,15 +283,11 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         const int e = tid + r * kSetupThreads;
         gv[r] = (e < g * NM) ? dr->Cgd[(e % NM) * kMaxGate + e / NM] : 0.0;
     }
-    const double cv = (tid < kMaxDot * kMaxDot) ? dr->Cdd[tid] : 0.0;
-    double m4[4], row[kMaxDot];
+    double m4[4];
     if (!pixel_wave) {
         const int j = tid & 15, b = tid >> 4;
 #pragma unroll
         for (int q = 0; q < 4; ++q) m4[q] = dr->Cdd[(4 * b + q) * kMaxDot + j];
-        const int r = tid & 15;
-#pragma unroll
-        for (int q = 0; q < kMaxDot; ++q) row[q] = dr->Cdd[r * kMaxDot + q];
     }
     double v0 = 0.0, v1 = 0.0;
     if (NM == 16 && pixel_wave && !vg.on) {
@@ -304,25 +299,26 @@ __global__ __launch_bounds__(kSetupThreads, CLOSED ? 3 : 4) void k_setup(DiagRec
         const int e = tid + r * kSetupThreads;
         if (e < g * NM) sG[e] = gv[r];
     }
-    if (tid < kMaxDot * kMaxDot) sCdd[tid] = cv;
     if (tid < 4) cnt[tid] = 0;
     if (!pixel_wave) {
+        // wave 0 holds all of C_dd (lane 16 b + j: column j of rows
+        // 4 b .. 4 b + 3): the input into LDS for the pixel waves' QP, C_dd 1
+        // by row sums within each DPP row, 1^T C_dd 1 over the four rows of
+        // DPP rows, then identity rows and columns past n for the inverse
         const int j = tid & 15, b = tid >> 4;
+        double ct = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int i = 4 * b + q;
+            sCdd[i * kMaxDot + j] = m4[q];
+            const double ri = row_sum((i < n && j < n) ? m4[q] : 0.0);
+            if (j == 0) sc[i] = ri;
+            ct += ri;
             m4[q] = (i < n && j < n) ? m4[q] : (i == j ? 1.0 : 0.0);
         }
-        // C_dd 1 and 1^T C_dd 1 (lanes 0..15, row r = lane)
-        const int r = tid & 15;
-        double c = 0.0;
-#pragma unroll
-        for (int q = 0; q < kMaxDot; ++q) c += (r < n && q < n) ? row[q] : 0.0;
-        double oc = c;
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) oc += __shfl_xor(oc, off, 16);
-        if (tid < kMaxDot) sc[r] = c;
-        if (tid == 0) red[4] = oc;
+        ct += __shfl_xor(ct, 16, 64);
+        ct += __shfl_xor(ct, 32, 64);
+        if (tid == 0) red[4] = ct;
     }
     __syncthreads();
     const double one_c = red[4];
