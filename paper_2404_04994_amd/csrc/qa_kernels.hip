@@ -897,9 +897,11 @@ __global__ __launch_bounds__(256) void k_soft_fwd_tab(const DiagRec *__restrict_
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
     for (int64_t p = gid; p < P; p += ngroups) {
         const PixRec *r = pr + p;
+        // g0: lane l of the group reads entry l mod NM, then broadcasts
+        // within the group (one read per lane instead of NM)
+        const double gl = r->g0[lane & (NM - 1)];
         double g0[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) g0[i] = r->g0[i];
+        static_for_dev<0, NM>([&](auto ic) { g0[decltype(ic)::value] = lane_bcast<LG, decltype(ic)::value>(gl); });
         double e[CPL];
         uint32_t st[CPL];
         const uint32_t fm = r->free;
@@ -1132,13 +1134,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CPL > 0 ? 3
             zd = (double)sr->n0[d] - s;
         }
         double z[NM], g0[NM], gb[NM];
-        double gnb = 0.0;
         static_for_dev<0, NM>([&](auto I) { z[I] = lane_bcast<LG, I>(zd); });
-#pragma unroll
-        for (int i = 0; i < NM; ++i) {
-            gb[i] = (i < n) ? gbar[p * n + i] : 0.0;
-            gnb += gb[i] * sr->nb[i];
-        }
+        // dL/d<n> and <n> - n0 of the pixel: lane d reads entry d, then
+        // broadcasts within the group (one read each per lane instead of NM)
+        const double gbd = d < n ? gbar[p * n + d] : 0.0;
+        const double gnd = gbd * sr->nb[d];
+        double gnb = 0.0;
+        static_for_dev<0, NM>([&](auto I) {
+            gb[I] = lane_bcast<LG, I>(gbd);
+            gnb += lane_bcast<LG, I>(gnd);
+        });
         // g0 = A z, U(n0) = 1/2 z^T g0
         double gd = 0.0;
 #pragma unroll
