@@ -788,9 +788,11 @@ __global__ __launch_bounds__(256) void k_soft_fwd(const DiagRec *__restrict__ dr
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
     for (int64_t p = gid; p < P; p += ngroups) {
         const PixRec *r = pr + p;
+        // g0: lane l of the group reads entry l mod NM, then broadcasts
+        // within the group (one read per lane instead of NM)
+        const double gl = r->g0[lane & (NM - 1)];
         double g0[NM], sv[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) g0[i] = r->g0[i];
+        static_for_dev<0, NM>([&](auto ic) { g0[decltype(ic)::value] = lane_bcast<LG, decltype(ic)::value>(gl); });
         double emin, Z;
         soft_sums<LG, NM>(sA, g0, r->u0, r->free, r->k, lane, kT, emin, Z, sv);
         if (lane == 0) {
@@ -990,9 +992,11 @@ __global__ __launch_bounds__(256) void k_score_tab(const DiagRec *__restrict__ d
     const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) >> LG;
     for (int64_t p = gid; p < P; p += ngroups) {
         const PixRec *r = pr + p;
+        // g0: lane l of the group reads entry l mod NM, then broadcasts
+        // within the group (one read per lane instead of NM)
+        const double gl = r->g0[lane & (NM - 1)];
         double g0[NM];
-#pragma unroll
-        for (int i = 0; i < NM; ++i) g0[i] = r->g0[i];
+        static_for_dev<0, NM>([&](auto ic) { g0[decltype(ic)::value] = lane_bcast<LG, decltype(ic)::value>(gl); });
         double e[CPL];
         uint32_t st[CPL];
         tab_energies<LG, NM, CPL>(sH, g0, r->u0, r->free, r->k, lane, e, st);
