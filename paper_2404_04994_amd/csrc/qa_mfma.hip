@@ -913,6 +913,13 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
 #pragma unroll
         for (int e4 = 0; e4 < 4; ++e4) ng += __popcll(__ballot(lb[e4] <= thr_g));
         const bool by_guess = ng <= 32;
+        // wave priority by the pixel's rows: the kernel ends with the waves
+        // whose pixels score more than one tile of rows, so while the SIMDs
+        // are still shared those waves issue first (0: one tile, 2: two,
+        // 3: more, and the near-tie re-score below)
+        if (ng > 32) __builtin_amdgcn_s_setprio(3);
+        else if (ng > 16) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
         if (by_guess) {
             list_rows(thr_g, -1);
         } else {
@@ -1226,6 +1233,7 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
         // keeping the smallest (ties to the lexicographically smallest
         // state) ----
         ++nflag;
+        __builtin_amdgcn_s_setprio(3);
         const float thr = e1 + 2.0f * delta;
         double c1best = INFINITY, c2best = INFINITY;
         uint32_t cbest = 0;
