@@ -913,13 +913,19 @@ __global__ __launch_bounds__(256, QA_BOUND_WAVES(PREC, MODE)) void k_score_bound
 #pragma unroll
         for (int e4 = 0; e4 < 4; ++e4) ng += __popcll(__ballot(lb[e4] <= thr_g));
         const bool by_guess = ng <= 32;
-        // wave priority by the pixel's rows: the kernel ends with the waves
-        // whose pixels score more than one tile of rows, so while the SIMDs
-        // are still shared those waves issue first (0: one tile, 2: two,
-        // 3: more, and the near-tie re-score below)
-        if (ng > 32) __builtin_amdgcn_s_setprio(3);
-        else if (ng > 16) __builtin_amdgcn_s_setprio(2);
-        else __builtin_amdgcn_s_setprio(0);
+        // wave priority by the wave's remaining work: the kernel ends with
+        // the waves whose pixels score more than one tile of rows and with
+        // those that still hold a pixel after this one, so while the SIMDs
+        // are shared those waves issue first (two levels for a pixel of more
+        // than one tile, one for a pixel still to come; 3 in the near-tie
+        // re-score below)
+        {
+            const int lv = __builtin_amdgcn_readfirstlane((ng > 16 ? 2 : 0) + (p + nwaves < P ? 1 : 0));
+            if (lv == 3) __builtin_amdgcn_s_setprio(3);
+            else if (lv == 2) __builtin_amdgcn_s_setprio(2);
+            else if (lv == 1) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
+        }
         if (by_guess) {
             list_rows(thr_g, -1);
         } else {
